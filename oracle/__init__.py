@@ -1,0 +1,210 @@
+"""FP64 CPU oracle for the split SL-MPP5 Vlasov sweeps -- TEST INFRASTRUCTURE.
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  The product path (the HIP library and its Python
+binding) never imports, loads or calls it.
+
+This module is a ctypes shim over ``liboracle_vlasov.so`` (plain C, FP64,
+OpenMP over lines).  Arrays are numpy float64 in the layout
+``f[ix][iy][iz][jx][jy][jz]`` (jz fastest); fields are float32
+``g[3][nx][ny][nz]``.  What each routine computes, and the passage of the
+paper it follows, is documented in ``vlasov_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle_vlasov.so")
+_lib = None
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+c_float_p = ctypes.POINTER(ctypes.c_float)
+
+
+class Grid(ctypes.Structure):
+    """Own copy of the grid description (shares nothing with the library)."""
+
+    _fields_ = [("n", ctypes.c_int * 3), ("nu", ctypes.c_int * 3),
+                ("L", ctypes.c_double * 3), ("umax", ctypes.c_double * 3)]
+
+    @classmethod
+    def make(cls, n, nu, L=(1.0, 1.0, 1.0), umax=(1.0, 1.0, 1.0)):
+        g = cls()
+        for a in range(3):
+            g.n[a] = int(n[a])
+            g.nu[a] = int(nu[a])
+            g.L[a] = float(L[a])
+            g.umax[a] = float(umax[a])
+        return g
+
+    @property
+    def shape(self):
+        return tuple(self.n) + tuple(self.nu)
+
+    def dx(self, a):
+        return self.L[a] / self.n[a]
+
+    def du(self, a):
+        return 2.0 * self.umax[a] / self.nu[a]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b  # noqa: F401  (compile on first use)
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        L.vor_median3.restype = ctypes.c_double
+        L.vor_median3.argtypes = [ctypes.c_double] * 3
+        L.vor_minmod4.restype = ctypes.c_double
+        L.vor_minmod4.argtypes = [ctypes.c_double] * 4
+        L.vor_sl5_weights.restype = None
+        L.vor_sl5_weights.argtypes = [ctypes.c_double, c_double_p]
+        L.vor_mp5_limit.restype = ctypes.c_double
+        L.vor_mp5_limit.argtypes = [ctypes.c_double] * 6
+        L.vor_split_shift.restype = None
+        L.vor_split_shift.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_long), c_double_p]
+        L.vor_interface_flux.restype = ctypes.c_double
+        L.vor_interface_flux.argtypes = [c_double_p, ctypes.c_long, ctypes.c_long, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int]
+        L.vor_sweep_line_opt.restype = None
+        L.vor_sweep_line_opt.argtypes = [c_double_p, c_double_p, ctypes.c_long, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int, c_double_p]
+        L.vor_position_shift.restype = ctypes.c_double
+        L.vor_position_shift.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_long,
+                                         ctypes.c_double]
+        L.vor_velocity_shift.restype = ctypes.c_double
+        L.vor_velocity_shift.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_float,
+                                         ctypes.c_double]
+        L.vor_advect_position.restype = ctypes.c_int
+        L.vor_advect_position.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, c_double_p,
+                                          c_double_p, ctypes.c_double]
+        L.vor_advect_velocity.restype = ctypes.c_int
+        L.vor_advect_velocity.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, ctypes.c_int,
+                                          c_double_p, c_double_p, c_float_p, ctypes.c_double,
+                                          c_double_p]
+        L.vor_step.restype = ctypes.c_int
+        L.vor_step.argtypes = [ctypes.POINTER(Grid), ctypes.c_int, c_double_p, c_double_p,
+                               c_double_p, c_float_p, c_float_p, ctypes.c_double,
+                               ctypes.c_double, c_double_p]
+        L.vor_moments.restype = ctypes.c_int
+        L.vor_moments.argtypes = [ctypes.POINTER(Grid), c_double_p, c_double_p, c_double_p,
+                                  c_double_p]
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(c_double_p) if a is not None else None
+
+
+def _fp(a):
+    return a.ctypes.data_as(c_float_p) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+# --- scalar pieces -------------------------------------------------------------
+
+def median3(x, y, z):
+    return lib().vor_median3(x, y, z)
+
+
+def minmod4(w, x, y, z):
+    return lib().vor_minmod4(w, x, y, z)
+
+
+def sl5_weights(mu: float) -> np.ndarray:
+    w = np.zeros(5)
+    lib().vor_sl5_weights(mu, _dp(w))
+    return w
+
+
+def mp5_limit(fhat, a, b, c, d, e) -> float:
+    return lib().vor_mp5_limit(fhat, a, b, c, d, e)
+
+
+def split_shift(s: float):
+    N = ctypes.c_long()
+    nu = ctypes.c_double()
+    lib().vor_split_shift(s, ctypes.byref(N), ctypes.byref(nu))
+    return N.value, nu.value
+
+
+def interface_flux(line, j, nu, periodic=True, limiter=True) -> float:
+    line = _f64(line)
+    return lib().vor_interface_flux(_dp(line), line.size, j, nu, int(periodic), int(limiter))
+
+
+def sweep_line(line, s, periodic=True, limiter=True):
+    """Advance one 1D line by the shift s (cells); returns (new_line, outflow)."""
+    line = _f64(line)
+    out = np.empty_like(line)
+    ofl = ctypes.c_double(0.0)
+    lib().vor_sweep_line_opt(_dp(line), _dp(out), line.size, float(s), int(periodic),
+                             int(limiter), ctypes.byref(ofl))
+    return out, ofl.value
+
+
+# --- 6D operators -------------------------------------------------------------
+
+def position_shift(grid: Grid, axis: int, j: int, dt_over_a2: float) -> float:
+    return lib().vor_position_shift(ctypes.byref(grid), axis, j, dt_over_a2)
+
+
+def velocity_shift(grid: Grid, axis: int, ga: float, dt: float) -> float:
+    return lib().vor_velocity_shift(ctypes.byref(grid), axis, ga, dt)
+
+
+def advect_position(grid: Grid, axis: int, f, dt_over_a2: float):
+    f = _f64(f)
+    out = np.empty_like(f)
+    _check(lib().vor_advect_position(ctypes.byref(grid), axis, _dp(f), _dp(out), dt_over_a2),
+           "advect_position")
+    return out
+
+
+def advect_velocity(grid: Grid, axis: int, f, g, dt: float, vbc: int = 0, outflow=None):
+    """Velocity sweep; ``outflow`` (float64 [cells]) is accumulated in place."""
+    f = _f64(f)
+    g = np.ascontiguousarray(g, dtype=np.float32)
+    out = np.empty_like(f)
+    _check(lib().vor_advect_velocity(ctypes.byref(grid), axis, vbc, _dp(f), _dp(out), _fp(g),
+                                     dt, _dp(outflow)), "advect_velocity")
+    return out
+
+
+def step(grid: Grid, f, g_n, g_np1, dt: float, a2inv: float = 1.0, vbc: int = 0, outflow=None):
+    """One Strang-split step (Eq. 5); ``outflow`` is accumulated in place."""
+    f = _f64(f)
+    out = np.empty_like(f)
+    work = np.empty_like(f)
+    g_n = np.ascontiguousarray(g_n, dtype=np.float32)
+    g_np1 = np.ascontiguousarray(g_np1, dtype=np.float32)
+    _check(lib().vor_step(ctypes.byref(grid), vbc, _dp(f), _dp(out), _dp(work), _fp(g_n),
+                          _fp(g_np1), dt, a2inv, _dp(outflow)), "step")
+    return out
+
+
+def moments(grid: Grid, f):
+    """Returns (rho [cells], umean [3, cells], mass)."""
+    f = _f64(f)
+    nx = grid.n[0] * grid.n[1] * grid.n[2]
+    rho = np.empty(nx)
+    um = np.empty(3 * nx)
+    mass = ctypes.c_double()
+    _check(lib().vor_moments(ctypes.byref(grid), _dp(f), _dp(rho), _dp(um), ctypes.byref(mass)),
+           "moments")
+    return rho.reshape(tuple(grid.n)), um.reshape((3,) + tuple(grid.n)), mass.value

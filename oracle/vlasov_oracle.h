@@ -1,0 +1,46 @@
+/*
+ * FP64 CPU oracle (test infrastructure only; see vlasov_oracle.c).
+ * Independent of the HIP library: this header is included by the oracle
+ * sources alone.
+ */
+#ifndef VLASOV_ORACLE_H
+#define VLASOV_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* spatial cells n[3] in a periodic box [0, L), velocity cells nu[3] on
+ * [-umax, umax) per axis */
+typedef struct {
+    int n[3];
+    int nu[3];
+    double L[3];
+    double umax[3];
+} vor_grid;
+
+double vor_median3(double x, double y, double z);
+double vor_minmod4(double w, double x, double y, double z);
+void vor_sl5_weights(double mu, double w[5]);
+double vor_mp5_limit(double fhat, double a, double b, double c, double d, double e);
+void vor_split_shift(double s, long* N, double* nu);
+double vor_interface_flux(const double* f, long M, long j, double nu, int periodic, int limiter);
+void vor_sweep_line_opt(const double* f, double* out, long M, double s, int periodic,
+                        int limiter, double* outflow);
+void vor_sweep_line(const double* f, double* out, long M, double s, int periodic, double* outflow);
+
+double vor_position_shift(const vor_grid* g, int a, long j, double dt_over_a2);
+double vor_velocity_shift(const vor_grid* g, int a, float ga, double dt);
+int vor_check_grid(const vor_grid* g);
+int vor_advect_position(const vor_grid* g, int a, const double* fin, double* fout,
+                        double dt_over_a2);
+int vor_advect_velocity(const vor_grid* g, int a, int vbc, const double* fin, double* fout,
+                        const float* gfield, double dt, double* outflow);
+int vor_step(const vor_grid* g, int vbc, const double* fin, double* fout, double* work,
+             const float* g_n, const float* g_np1, double dt, double a2inv, double* outflow);
+int vor_moments(const vor_grid* g, const double* f, double* rho, double* umean, double* mass);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
