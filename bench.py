@@ -1,0 +1,221 @@
+"""Throughput of the split SL-MPP5 Vlasov step on one MI355X.
+
+One step is the nine sweeps of Eq. (5) (half kicks ux,uy,uz; drifts z,y,x;
+half kicks ux,uy,uz) over the whole 6D grid.  The default workload is the
+throughput shape, 64^3 spatial x 32^3 velocity cells (8.59e9 cells, 34.4 GB
+per FP32 copy), with the seeded initial condition and drifting potential of
+``paper_2110_15867_amd.inputs``.  Inputs and all fields are resident in HBM
+before the timed region.
+
+Prints ONE JSON line: cell-updates/s per full step, the algorithmic HBM rate,
+a roofline entry for the slowest sweep (HIP events on the launch stream) and
+the FP64 CPU oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes_per_cell(prec: int, nuz: int) -> float:
+    """One read and one write of f per sweep (codes, plus scales for FP16/BF16)."""
+    if prec == 0:
+        return 8.0
+    return 2.0 * (2.0 + 4.0 / nuz)
+
+
+def cpu_baseline(seconds: float = 12.0):
+    """FP64 oracle Strang step on the 16^3 x 16^3 workload (same recipe), host cores."""
+    import numpy as np
+
+    import oracle
+    from paper_2110_15867_amd import inputs
+
+    w = inputs.workload(1)
+    g = oracle.Grid.make(w.n, w.nu, w.L, w.umax)
+    f = inputs.initial_f(w)
+    pot = inputs.potential(w)
+    steps, t_used = 0, 0.0
+    while t_used < seconds and steps < 20:
+        gn = inputs.accel_field(w, pot, steps * w.dt)
+        gnp1 = inputs.accel_field(w, pot, (steps + 1) * w.dt)
+        t0 = time.perf_counter()
+        f = oracle.step(g, f, gn, gnp1, w.dt)
+        t_used += time.perf_counter() - t0
+        steps += 1
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {
+        "value": w.cells * steps / t_used,
+        "unit": "cell-updates/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"FP64 oracle Strang step on 16^3x16^3 cells (same recipe), {steps} steps, "
+                  f"{t_used:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--workload", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the sweeps shard along space across GPUs "
+              "(design only, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2110_15867_amd import inputs
+    from paper_2110_15867_amd import vlasov as V
+
+    prec = {"f32": V.F32, "f16": V.F16, "bf16": V.BF16}[args.prec]
+    w = inputs.workload(args.workload)
+    grid = V.make_grid(w.n, w.nu, w.L, w.umax)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    K, W = args.steps, args.warmup
+    _log(f"bench: {w.name}, {w.cells:.3e} cells, prec {args.prec}, warmup {W}, steps {K}")
+
+    # ---- inputs resident in HBM ----
+    f0 = inputs.initial_f32_device(w, dev)
+    state = V.encode(grid, prec, f0)
+    if prec != V.F32:
+        del f0
+    pot = inputs.potential(w)
+    nfield = W + 2 * K + 1
+    fields = [torch.from_numpy(inputs.accel_field(w, pot, n * w.dt)).to(dev)
+              for n in range(nfield)]
+    out = V.empty_state(grid, prec, dev)
+    work_bytes = V.vlasov_step_workspace_bytes(grid, prec)
+    work = torch.empty(work_bytes, dtype=torch.uint8, device=dev)
+    outflow = torch.zeros(tuple(w.n), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    _log("bench: inputs ready")
+
+    def one_step(src, dst, n):
+        V.vlasov_step(grid, prec, V.VBC_OUTFLOW, src.f, src.scale, dst.f, dst.scale,
+                      fields[n], fields[n + 1], w.dt, 1.0, work, work_bytes, outflow, stream)
+
+    n = 0
+    for _ in range(W):
+        one_step(state, out, n)
+        state, out = out, state
+        n += 1
+    torch.cuda.synchronize()
+    _log("bench: warmup done")
+
+    # ---- timed region: K whole steps through vlasov_step ----
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    ev[0].record(stream)
+    for k in range(K):
+        one_step(state, out, n)
+        state, out = out, state
+        n += 1
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    step_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(K)]
+    total_ms = ev[0].elapsed_time(ev[K])
+    _log(f"bench: timed {K} steps, {total_ms:.1f} ms (wall {t_wall * 1e3:.1f} ms)")
+
+    # ---- per-sweep durations: the same nine launches, events between them ----
+    names = ["ux", "uy", "uz", "z", "y", "x", "ux", "uy", "uz"]
+    per = {k: [] for k in ["ux", "uy", "uz", "z", "y", "x"]}
+    wf = V.empty_state(grid, prec, dev)
+    bufA, bufB, bufC = state, out, wf      # input, and the two ping-pong targets
+    for _ in range(K):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(10)]
+        src, b = bufA, 0
+        gn, gnp1 = fields[n], fields[n + 1]
+        evs[0].record(stream)
+        for i, nm in enumerate(names):
+            dst = (bufB, bufC)[b]
+            if nm in ("x", "y", "z"):
+                getattr(V, f"vlasov_advect_{nm}")(grid, prec, src.f, src.scale, dst.f, dst.scale,
+                                                  w.dt, stream)
+            else:
+                field = gn if i < 3 else gnp1
+                getattr(V, f"vlasov_advect_{nm}")(grid, prec, V.VBC_OUTFLOW, src.f, src.scale,
+                                                  dst.f, dst.scale, field, 0.5 * w.dt, outflow,
+                                                  stream)
+            evs[i + 1].record(stream)
+            src = dst
+            b ^= 1
+        torch.cuda.synchronize()
+        for i, nm in enumerate(names):
+            per[nm].append(evs[i].elapsed_time(evs[i + 1]))
+        bufA, bufB = bufB, bufA            # nine sweeps end in bufB
+        n += 1
+    state, out = bufA, bufB
+    del wf, bufC
+    avg = {k: statistics.mean(v) for k, v in per.items()}
+    dominant = max(avg, key=avg.get)
+    bpc = algorithmic_bytes_per_cell(prec, w.nu[2])
+    launch_bytes = bpc * w.cells
+    achieved = launch_bytes / (avg[dominant] * 1e-3) / 1e9
+    _log("bench: per-sweep ms " + json.dumps({k: round(v, 3) for k, v in avg.items()}))
+
+    value = w.cells * K / (total_ms * 1e-3)
+    step_bytes = 9 * launch_bytes
+    res = {
+        "metric": "6D phase-space cell-updates/sec per full step",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": total_ms / K,
+        "median_ms_per_step": statistics.median(step_ms),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {V.F32: "f32", V.F16: "f16 storage, f32 math",
+                  V.BF16: "bf16 storage, f32 math"}[prec],
+        "data": "synthetic (seeded Fermi-Dirac-like f0 with random density modes, "
+                "drifting 4-mode potential)",
+        "config": {"workload": w.name, "nx": list(w.n), "nu": list(w.nu), "L": list(w.L),
+                   "dt": w.dt, "sweeps_per_step": 9, "storage": args.prec},
+        "hbm_tbps_algorithmic": step_bytes / (total_ms / K * 1e-3) / 1e12,
+        "sweep_ms": {k: round(v, 4) for k, v in avg.items()},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"sweep {dominant}",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+    }
+    del state, out, work, fields
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        _log("bench: timing the CPU oracle")
+        res["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

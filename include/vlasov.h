@@ -1,0 +1,177 @@
+/*
+ * libvlasov -- split SL-MPP5 advection of the distribution function f(x,u)
+ * on a six-dimensional phase-space grid, for AMD Instinct MI355X (gfx950).
+ *
+ * Method (Yoshikawa, Tanaka & Yoshida, "A 400 trillion-grid Vlasov
+ * simulation on Fugaku supercomputer", SC'21):
+ *   - Vlasov equation, Eq. (1), split into six 1D advections: position
+ *     sweeps along x, y, z with speed u_i / a^2 (Eq. 3) and velocity sweeps
+ *     along ux, uy, uz with speed g_i = -d(phi)/dx_i (Eq. 4), section 5.1.1;
+ *   - one full step composed as in Eq. (5);
+ *   - each 1D operator is SL-MPP5 (section 5.2): fifth-order finite volume,
+ *     conservative semi-Lagrangian interface flux (exact integral of the
+ *     quartic reconstruction over the upwind departure interval), limited by
+ *     the Suresh-Huynh monotonicity-preserving bounds (alpha = 4) and a
+ *     positivity clamp, one flux evaluation per cell per step;
+ *   - FP32 flux arithmetic (section 5.1.1); FP64 only for reductions;
+ *   - velocity moments per spatial cell without data exchange (5.1.3).
+ *
+ * Data layout (List 1 of section 5.3 without the per-cell header):
+ *   f[ix][iy][iz][jx][jy][jz], jz fastest; cell centres x_i = (i+1/2) L/n,
+ *   u_j = -umax + (j+1/2) du with du = 2 umax / nu.  The header fields of
+ *   List 1 (dens, mean velocity) are separate FP64 arrays [nx][ny][nz].
+ *
+ * Storage precisions: FP32, or FP16 / BF16 with one FP32 scale per
+ * uz-line (the nu_z values of one (ix,iy,iz,jx,jy)): value = code * scale,
+ * scale = largest |value| on the line.  Scale arrays have
+ * nx*ny*nz*nux*nuy entries and are NULL for FP32.
+ *
+ * Conventions for every entry point:
+ *   - Pointers to arrays are DEVICE pointers owned by the caller; the grid
+ *     is a HOST pointer read during the call only.  The library keeps no
+ *     reference after returning and allocates nothing: scratch space is the
+ *     caller's workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls enqueue work and return without synchronising.
+ *   - Out-of-place only: an output that overlaps an input is rejected.
+ *   - Results are bitwise reproducible for identical inputs (no atomics,
+ *     fixed-order reductions).
+ *   - Errors are returned as negative codes; nothing aborts.  Argument
+ *     checks are host-side and O(1); a launch failure maps to
+ *     VLASOV_ERR_DEVICE.  Array contents are not inspected: f must be finite
+ *     and non-negative for the positivity guarantee.
+ *   - Calls are reentrant; the library holds no global state.
+ */
+#ifndef LIBVLASOV_H
+#define LIBVLASOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VLASOV_ABI_VERSION 1
+
+/* Phase-space grid: n[3] spatial cells of the periodic box [0, L) and nu[3]
+ * velocity cells of [-umax, umax) per axis (domain of section 5.1.3). */
+typedef struct vlasov_grid {
+    int32_t n[3];
+    int32_t nu[3];
+    double L[3];
+    double umax[3];
+} vlasov_grid;
+
+typedef enum vlasov_prec {
+    VLASOV_F32 = 0,   /* float */
+    VLASOV_F16 = 1,   /* IEEE half code per value + FP32 scale per uz-line */
+    VLASOV_BF16 = 2   /* bfloat16 code per value + FP32 scale per uz-line */
+} vlasov_prec;
+
+/* Velocity-space boundary.  OUTFLOW: vacuum outside [-umax, umax), the
+ * content leaving through a face is tallied.  PERIODIC: wrap (used to test
+ * invariants; not physical). */
+typedef enum vlasov_vbc {
+    VLASOV_VBC_OUTFLOW = 0,
+    VLASOV_VBC_PERIODIC = 1
+} vlasov_vbc;
+
+enum {
+    VLASOV_OK = 0,
+    VLASOV_ERR_NULL = -1,       /* a required pointer is NULL */
+    VLASOV_ERR_SHAPE = -2,      /* grid sizes/extents invalid or unsupported */
+    VLASOV_ERR_PREC = -3,       /* unknown precision or vbc, or scale missing */
+    VLASOV_ERR_ALIAS = -4,      /* an output overlaps an input */
+    VLASOV_ERR_NONFINITE = -5,  /* dt, a^-2 or the derived shift factor is not finite */
+    VLASOV_ERR_DEVICE = -6,     /* HIP launch or runtime error */
+    VLASOV_ERR_WORKSPACE = -7   /* workspace NULL or smaller than required */
+};
+
+/* Version of this interface (VLASOV_ABI_VERSION). */
+int vlasov_abi_version(void);
+
+/* Static description of an error code; never NULL. */
+const char* vlasov_strerror(int code);
+
+/* Storage bytes of one copy of f (codes only) and of its scale array. */
+size_t vlasov_f_bytes(const vlasov_grid* grid, vlasov_prec prec);
+size_t vlasov_scale_bytes(const vlasov_grid* grid, vlasov_prec prec);
+
+/*
+ * Position sweeps (Eq. 3): advance f along x, y or z over dt.  The shift of
+ * the line with velocity index j is s_j = u_j * dt_over_a2 / dx in cells
+ * (dt_over_a2 = dt / a(t)^2; a = 1 gives dt).  s = N + nu is split into an
+ * integer part applied as an exact translation and a fraction applied by the
+ * SL-MPP5 flux; the box is periodic.  Any |s| is accepted.
+ *   f_in / scale_in : input f (and its scales for F16/BF16)
+ *   f_out / scale_out : output f (and scales); must not overlap the inputs
+ */
+int vlasov_advect_x(const vlasov_grid* grid, vlasov_prec prec, const void* f_in,
+                    const float* scale_in, void* f_out, float* scale_out,
+                    double dt_over_a2, void* stream);
+int vlasov_advect_y(const vlasov_grid* grid, vlasov_prec prec, const void* f_in,
+                    const float* scale_in, void* f_out, float* scale_out,
+                    double dt_over_a2, void* stream);
+int vlasov_advect_z(const vlasov_grid* grid, vlasov_prec prec, const void* f_in,
+                    const float* scale_in, void* f_out, float* scale_out,
+                    double dt_over_a2, void* stream);
+
+/*
+ * Velocity sweeps (Eq. 4): advance f along ux, uy or uz over dt.  The shift
+ * of every line of spatial cell c is s = g[axis][c] * dt / du (the advection
+ * speed in velocity space is g = -grad phi).
+ *   g       : FP32 field [3][nx][ny][nz], device
+ *   outflow : FP64 [nx][ny][nz], device, or NULL.  With VBC_OUTFLOW the
+ *             content that leaves [-umax, umax) through the two faces of
+ *             this axis, in density units (sum of f times du^3), is ADDED to
+ *             outflow[c].  Untouched with VBC_PERIODIC.
+ */
+int vlasov_advect_ux(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc,
+                     const void* f_in, const float* scale_in, void* f_out, float* scale_out,
+                     const float* g, double dt, double* outflow, void* stream);
+int vlasov_advect_uy(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc,
+                     const void* f_in, const float* scale_in, void* f_out, float* scale_out,
+                     const float* g, double dt, double* outflow, void* stream);
+int vlasov_advect_uz(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc,
+                     const void* f_in, const float* scale_in, void* f_out, float* scale_out,
+                     const float* g, double dt, double* outflow, void* stream);
+
+/* Bytes of workspace vlasov_step needs: one intermediate copy of f plus its
+ * scales, 256-byte aligned. */
+size_t vlasov_step_workspace_bytes(const vlasov_grid* grid, vlasov_prec prec);
+
+/*
+ * One full step, Eq. (5):
+ *   f^{n+1} = D_uz D_uy D_ux(dt/2; g_np1) D_x D_y D_z(dt) D_uz D_uy D_ux(dt/2; g_n) f^n
+ * applied right to left: half kicks ux, uy, uz with the field at t^n, drifts
+ * z, y, x with dt * a2inv, half kicks ux, uy, uz with the field at t^{n+1}.
+ * Nine sweeps; intermediates ping-pong between f_out and work.
+ *   g_n, g_np1 : FP32 fields [3][nx][ny][nz] at t^n and t^{n+1}
+ *   a2inv      : a(t)^-2 for the drifts
+ *   work       : device workspace of at least vlasov_step_workspace_bytes
+ *   outflow    : as for the velocity sweeps (accumulated over the six kicks)
+ */
+int vlasov_step(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, const void* f_in,
+                const float* scale_in, void* f_out, float* scale_out, const float* g_n,
+                const float* g_np1, double dt, double a2inv, void* work, size_t work_bytes,
+                double* outflow, void* stream);
+
+/*
+ * Velocity moments per spatial cell (section 5.1.3), accumulated in FP64:
+ *   rho[c]      = sum_u f du^3
+ *   umean[a][c] = sum_u u_a f du^3 / rho[c]  (0 where rho[c] = 0); may be NULL
+ *   mass        = sum_c rho[c] dx^3 (device FP64 scalar); may be NULL
+ * rho and umean are FP64 device arrays [nx][ny][nz] and [3][nx][ny][nz].
+ */
+int vlasov_moments(const vlasov_grid* grid, vlasov_prec prec, const void* f, const float* scale,
+                   double* rho, double* umean, double* mass, void* stream);
+
+/* Deterministic FP64 sum of x[0..n) into *out (device pointers): a single
+ * work-group, fixed order.  Used for total mass and total outflow. */
+int vlasov_sum_f64(const double* x, int64_t n, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBVLASOV_H */

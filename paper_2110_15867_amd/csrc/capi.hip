@@ -1,0 +1,373 @@
+// C-ABI of libvlasov: argument checks, per-line shift tables and the launch
+// sequence of each entry point.  Declarations and their contracts are in
+// include/vlasov.h.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/vlasov.h"
+#include "launch.hpp"
+
+using namespace vlasov;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Dims {
+    long n[3], nu[3];
+    long cells, Nu, total;
+};
+
+bool dims_of(const vlasov_grid* g, Dims& d)
+{
+    if (g == nullptr) return false;
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] < 1 || g->nu[a] < 1) return false;
+        if (!(g->L[a] > 0.0) || !isfinite(g->L[a])) return false;
+        if (!(g->umax[a] > 0.0) || !isfinite(g->umax[a])) return false;
+        d.n[a] = g->n[a];
+        d.nu[a] = g->nu[a];
+    }
+    d.cells = d.n[0] * d.n[1] * d.n[2];
+    d.Nu = d.nu[0] * d.nu[1] * d.nu[2];
+    if (d.cells > 0x7fffffffL) return false;          // one work-group per cell
+    if (d.Nu > 0x7fffffffL) return false;
+    d.total = d.cells * d.Nu;
+    return true;
+}
+
+size_t elem_bytes(int prec) { return prec == VLASOV_F32 ? 4 : 2; }
+
+bool prec_ok(int prec) { return prec == VLASOV_F32 || prec == VLASOV_F16 || prec == VLASOV_BF16; }
+
+// Scaled storage keeps one scale per uz-line; the kernels spread a uz-line
+// over a power-of-two group of lanes.
+bool scaled_shape_ok(const Dims& d)
+{
+    const long z = d.nu[2];
+    return z >= 4 && z <= 64 && (z & (z - 1)) == 0;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb)
+{
+    if (a == nullptr || b == nullptr || na == 0 || nb == 0) return false;
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int vector_width(long nuz) { return nuz % 4 == 0 ? 4 : (nuz % 2 == 0 ? 2 : 1); }
+
+// Common checks of a sweep's storage arguments.
+int check_io(const Dims& d, int prec, const void* fin, const float* sin, const void* fout,
+             const float* sout)
+{
+    if (!prec_ok(prec)) return VLASOV_ERR_PREC;
+    if (fin == nullptr || fout == nullptr) return VLASOV_ERR_NULL;
+    if (!aligned16(fin) || !aligned16(fout)) return VLASOV_ERR_SHAPE;
+    const size_t fb = (size_t)d.total * elem_bytes(prec);
+    if (prec != VLASOV_F32) {
+        if (sin == nullptr || sout == nullptr) return VLASOV_ERR_PREC;
+        if (!scaled_shape_ok(d)) return VLASOV_ERR_SHAPE;
+        const size_t sb = (size_t)(d.total / d.nu[2]) * sizeof(float);
+        if (overlap(sout, sb, sin, sb) || overlap(sout, sb, fin, fb) || overlap(fout, fb, sin, sb))
+            return VLASOV_ERR_ALIAS;
+    }
+    if (overlap(fout, fb, fin, fb)) return VLASOV_ERR_ALIAS;
+    return VLASOV_OK;
+}
+
+int from_hip(hipError_t e) { return e == hipSuccess ? VLASOV_OK : VLASOV_ERR_DEVICE; }
+
+// Shift of the position sweep along axis a for velocity index j (Eq. 3):
+// s_j = u_j * dt a^-2 / dx with u_j the cell centre of velocity cell j.
+double position_shift(const vlasov_grid* g, int a, long j, double dt_over_a2)
+{
+#pragma clang fp contract(off)
+    const double dx = g->L[a] / g->n[a];
+    const double factor = dt_over_a2 / dx;
+    const double du = 2.0 * g->umax[a] / g->nu[a];
+    const double u = -g->umax[a] + (j + 0.5) * du;
+    return u * factor;
+}
+
+int run_position(const vlasov_grid* g, const Dims& d, int axis, int prec, const void* fin,
+                 const float* sin, void* fout, float* sout, double dt_over_a2, hipStream_t st)
+{
+    if (!isfinite(dt_over_a2)) return VLASOV_ERR_NONFINITE;
+    if (d.nu[axis] > kMaxShiftTable) return VLASOV_ERR_SHAPE;
+    PosArgs a;
+    memset(&a, 0, sizeof(a));
+    a.O = 1;
+    for (int b = 0; b < axis; ++b) a.O *= d.n[b];
+    a.M = (int)d.n[axis];
+    a.I = d.Nu;
+    for (int b = axis + 1; b < 3; ++b) a.I *= d.n[b];
+    a.Nu = d.Nu;
+    a.pst = axis == 0 ? d.nu[1] * d.nu[2] : (axis == 1 ? d.nu[2] : 1);
+    a.nshift = (int)d.nu[axis];
+    a.nuz = d.nu[2];
+    a.V = axis == 2 ? 1 : vector_width(d.nu[2]);
+    a.G = (int)(d.nu[2] / a.V);
+    for (long j = 0; j < d.nu[axis]; ++j) {
+        a.shift[j] = position_shift(g, axis, j, dt_over_a2);
+        if (!isfinite(a.shift[j])) return VLASOV_ERR_NONFINITE;
+    }
+    return from_hip(launch_position(prec, fin, sin, fout, sout, a, st));
+}
+
+int run_velocity(const vlasov_grid* g, const Dims& d, int axis, int prec, int vbc,
+                 const void* fin, const float* sin, void* fout, float* sout, const float* field,
+                 double dt, double* outflow, hipStream_t st)
+{
+    if (!isfinite(dt)) return VLASOV_ERR_NONFINITE;
+    const double du = 2.0 * g->umax[axis] / g->nu[axis];
+    const double factor = dt / du;
+    if (!isfinite(factor)) return VLASOV_ERR_NONFINITE;
+    VelArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = field + (long)axis * d.cells;
+    a.factor = factor;
+    a.M = (int)d.nu[axis];
+    a.nuz = d.nu[2];
+    a.periodic = vbc == VLASOV_VBC_PERIODIC;
+    a.outflow = outflow;
+    a.du3 = (2.0 * g->umax[0] / g->nu[0]) * (2.0 * g->umax[1] / g->nu[1]) *
+            (2.0 * g->umax[2] / g->nu[2]);
+    a.cells = d.cells;
+    if (axis == 2) {
+        a.I = 1;
+        a.nsub = d.nu[0] * d.nu[1];
+        a.V = 1;
+        a.G = 1;
+        return from_hip(launch_vel_uz(prec, fin, sin, fout, sout, a, st));
+    }
+    a.I = axis == 0 ? d.nu[1] * d.nu[2] : d.nu[2];
+    a.nsub = axis == 0 ? 1 : d.nu[0];
+    a.V = vector_width(d.nu[2]);
+    a.G = (int)(d.nu[2] / a.V);
+    return from_hip(launch_vel_strided(prec, fin, sin, fout, sout, a, st));
+}
+
+int advect_position(const vlasov_grid* g, int axis, int prec, const void* fin, const float* sin,
+                    void* fout, float* sout, double dt_over_a2, void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    const int rc = check_io(d, prec, fin, sin, fout, sout);
+    if (rc) return rc;
+    return run_position(g, d, axis, prec, fin, sin, fout, sout, dt_over_a2, (hipStream_t)stream);
+}
+
+int advect_velocity(const vlasov_grid* g, int axis, int prec, int vbc, const void* fin,
+                    const float* sin, void* fout, float* sout, const float* field, double dt,
+                    double* outflow, void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (vbc != VLASOV_VBC_OUTFLOW && vbc != VLASOV_VBC_PERIODIC) return VLASOV_ERR_PREC;
+    if (field == nullptr) return VLASOV_ERR_NULL;
+    const int rc = check_io(d, prec, fin, sin, fout, sout);
+    if (rc) return rc;
+    const size_t fb = (size_t)d.total * elem_bytes(prec);
+    if (overlap(fout, fb, field, 3 * d.cells * sizeof(float))) return VLASOV_ERR_ALIAS;
+    if (outflow != nullptr && overlap(fout, fb, outflow, d.cells * sizeof(double)))
+        return VLASOV_ERR_ALIAS;
+    return run_velocity(g, d, axis, prec, vbc, fin, sin, fout, sout, field, dt, outflow,
+                        (hipStream_t)stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int vlasov_abi_version(void) { return VLASOV_ABI_VERSION; }
+
+const char* vlasov_strerror(int code)
+{
+    switch (code) {
+        case VLASOV_OK: return "success";
+        case VLASOV_ERR_NULL: return "a required pointer is NULL";
+        case VLASOV_ERR_SHAPE: return "grid sizes, extents or alignment invalid or unsupported";
+        case VLASOV_ERR_PREC: return "unknown precision or velocity boundary, or scale array missing";
+        case VLASOV_ERR_ALIAS: return "an output overlaps an input";
+        case VLASOV_ERR_NONFINITE: return "time step or shift factor is not finite";
+        case VLASOV_ERR_DEVICE: return "HIP launch or runtime error";
+        case VLASOV_ERR_WORKSPACE: return "workspace missing or too small";
+        default: return "unknown error code";
+    }
+}
+
+size_t vlasov_f_bytes(const vlasov_grid* grid, vlasov_prec prec)
+{
+    Dims d;
+    if (!dims_of(grid, d) || !prec_ok(prec)) return 0;
+    return (size_t)d.total * elem_bytes(prec);
+}
+
+size_t vlasov_scale_bytes(const vlasov_grid* grid, vlasov_prec prec)
+{
+    Dims d;
+    if (!dims_of(grid, d) || !prec_ok(prec) || prec == VLASOV_F32) return 0;
+    return (size_t)(d.total / d.nu[2]) * sizeof(float);
+}
+
+int vlasov_advect_x(const vlasov_grid* g, vlasov_prec p, const void* fin, const float* sin,
+                    void* fout, float* sout, double dt_over_a2, void* stream)
+{
+    return advect_position(g, 0, p, fin, sin, fout, sout, dt_over_a2, stream);
+}
+int vlasov_advect_y(const vlasov_grid* g, vlasov_prec p, const void* fin, const float* sin,
+                    void* fout, float* sout, double dt_over_a2, void* stream)
+{
+    return advect_position(g, 1, p, fin, sin, fout, sout, dt_over_a2, stream);
+}
+int vlasov_advect_z(const vlasov_grid* g, vlasov_prec p, const void* fin, const float* sin,
+                    void* fout, float* sout, double dt_over_a2, void* stream)
+{
+    return advect_position(g, 2, p, fin, sin, fout, sout, dt_over_a2, stream);
+}
+
+int vlasov_advect_ux(const vlasov_grid* g, vlasov_prec p, vlasov_vbc vbc, const void* fin,
+                     const float* sin, void* fout, float* sout, const float* field, double dt,
+                     double* outflow, void* stream)
+{
+    return advect_velocity(g, 0, p, vbc, fin, sin, fout, sout, field, dt, outflow, stream);
+}
+int vlasov_advect_uy(const vlasov_grid* g, vlasov_prec p, vlasov_vbc vbc, const void* fin,
+                     const float* sin, void* fout, float* sout, const float* field, double dt,
+                     double* outflow, void* stream)
+{
+    return advect_velocity(g, 1, p, vbc, fin, sin, fout, sout, field, dt, outflow, stream);
+}
+int vlasov_advect_uz(const vlasov_grid* g, vlasov_prec p, vlasov_vbc vbc, const void* fin,
+                     const float* sin, void* fout, float* sout, const float* field, double dt,
+                     double* outflow, void* stream)
+{
+    return advect_velocity(g, 2, p, vbc, fin, sin, fout, sout, field, dt, outflow, stream);
+}
+
+size_t vlasov_step_workspace_bytes(const vlasov_grid* grid, vlasov_prec prec)
+{
+    Dims d;
+    if (!dims_of(grid, d) || !prec_ok(prec)) return 0;
+    size_t b = align_up((size_t)d.total * elem_bytes(prec));
+    if (prec != VLASOV_F32) b += align_up((size_t)(d.total / d.nu[2]) * sizeof(float));
+    return b;
+}
+
+int vlasov_step(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
+                const float* sin, void* fout, float* sout, const float* g_n, const float* g_np1,
+                double dt, double a2inv, void* work, size_t work_bytes, double* outflow,
+                void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (vbc != VLASOV_VBC_OUTFLOW && vbc != VLASOV_VBC_PERIODIC) return VLASOV_ERR_PREC;
+    if (g_n == nullptr || g_np1 == nullptr) return VLASOV_ERR_NULL;
+    int rc = check_io(d, prec, fin, sin, fout, sout);
+    if (rc) return rc;
+    if (!isfinite(dt) || !isfinite(a2inv) || !isfinite(dt * a2inv)) return VLASOV_ERR_NONFINITE;
+    for (int a = 0; a < 3; ++a)
+        if (d.nu[a] > kMaxShiftTable) return VLASOV_ERR_SHAPE;
+    const size_t need = vlasov_step_workspace_bytes(g, prec);
+    if (work == nullptr || work_bytes < need) return VLASOV_ERR_WORKSPACE;
+    const size_t fb = (size_t)d.total * elem_bytes(prec);
+    const size_t sb = prec == VLASOV_F32 ? 0 : (size_t)(d.total / d.nu[2]) * sizeof(float);
+    void* wf = work;
+    float* ws = prec == VLASOV_F32 ? nullptr : (float*)((char*)work + align_up(fb));
+    if (overlap(work, need, fin, fb) || overlap(work, need, fout, fb) ||
+        overlap(work, need, sin, sb) || overlap(work, need, sout, sb))
+        return VLASOV_ERR_ALIAS;
+    if (overlap(fout, fb, g_n, 3 * d.cells * sizeof(float)) ||
+        overlap(fout, fb, g_np1, 3 * d.cells * sizeof(float)))
+        return VLASOV_ERR_ALIAS;
+    hipStream_t st = (hipStream_t)stream;
+    const double h = 0.5 * dt;
+    const double dta = dt * a2inv;
+    // Eq. (5) right to left; buffers: in -> out -> work -> out -> ... -> out
+    struct Buf { const void* f; const float* s; };
+    Buf src{fin, sin};
+    void* dstf[2] = {fout, wf};
+    float* dsts[2] = {sout, ws};
+    int k = 0;
+    auto vel = [&](int axis, const float* field) {
+        const int r = run_velocity(g, d, axis, prec, vbc, src.f, src.s, dstf[k & 1], dsts[k & 1],
+                                   field, h, outflow, st);
+        src = Buf{dstf[k & 1], dsts[k & 1]};
+        ++k;
+        return r;
+    };
+    auto pos = [&](int axis) {
+        const int r = run_position(g, d, axis, prec, src.f, src.s, dstf[k & 1], dsts[k & 1], dta, st);
+        src = Buf{dstf[k & 1], dsts[k & 1]};
+        ++k;
+        return r;
+    };
+    if ((rc = vel(0, g_n))) return rc;
+    if ((rc = vel(1, g_n))) return rc;
+    if ((rc = vel(2, g_n))) return rc;
+    if ((rc = pos(2))) return rc;
+    if ((rc = pos(1))) return rc;
+    if ((rc = pos(0))) return rc;
+    if ((rc = vel(0, g_np1))) return rc;
+    if ((rc = vel(1, g_np1))) return rc;
+    if ((rc = vel(2, g_np1))) return rc;
+    return VLASOV_OK;
+}
+
+int vlasov_moments(const vlasov_grid* g, vlasov_prec prec, const void* f, const float* scale,
+                   double* rho, double* umean, double* mass, void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (!prec_ok(prec)) return VLASOV_ERR_PREC;
+    if (f == nullptr || rho == nullptr) return VLASOV_ERR_NULL;
+    if (!aligned16(f)) return VLASOV_ERR_SHAPE;
+    if (prec != VLASOV_F32) {
+        if (scale == nullptr) return VLASOV_ERR_PREC;
+        if (!scaled_shape_ok(d)) return VLASOV_ERR_SHAPE;
+    }
+    const size_t nb = (size_t)d.cells * sizeof(double);
+    if (umean != nullptr && overlap(rho, nb, umean, 3 * nb)) return VLASOV_ERR_ALIAS;
+    if (mass != nullptr && (overlap(mass, 8, rho, nb) || overlap(mass, 8, umean, 3 * nb)))
+        return VLASOV_ERR_ALIAS;
+    MomArgs a;
+    memset(&a, 0, sizeof(a));
+    a.cells = d.cells;
+    a.Nu = d.Nu;
+    a.nuz = d.nu[2];
+    a.du3 = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        a.nu[k] = (int)d.nu[k];
+        a.umin[k] = -g->umax[k];
+        a.du[k] = 2.0 * g->umax[k] / g->nu[k];
+        a.du3 *= a.du[k];
+    }
+    a.rho = rho;
+    a.umean = umean;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = from_hip(launch_moments(prec, f, scale, a, st));
+    if (rc || mass == nullptr) return rc;
+    const double dx3 = (g->L[0] / g->n[0]) * (g->L[1] / g->n[1]) * (g->L[2] / g->n[2]);
+    return from_hip(launch_sum(rho, d.cells, dx3, mass, st));
+}
+
+int vlasov_sum_f64(const double* x, int64_t n, double* out, void* stream)
+{
+    if (x == nullptr || out == nullptr) return VLASOV_ERR_NULL;
+    if (n < 0) return VLASOV_ERR_SHAPE;
+    if (overlap(out, 8, x, (size_t)n * 8)) return VLASOV_ERR_ALIAS;
+    return from_hip(launch_sum(x, n, 1.0, out, (hipStream_t)stream));
+}
+
+}  // extern "C"

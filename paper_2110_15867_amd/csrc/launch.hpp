@@ -1,0 +1,63 @@
+// Host-side launch descriptors shared by the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vlasov {
+
+constexpr int kMaxShiftTable = 256;   // velocity cells per axis a position sweep supports
+
+// Position sweep along one spatial axis (Eq. 3).
+struct PosArgs {
+    long O;          // lines before the axis (product of earlier spatial sizes)
+    long I;          // inner elements after the axis
+    int M;           // cells along the axis
+    long Nu;         // velocity cells per spatial cell
+    long pst;        // stride of the velocity index that sets the shift
+    int nshift;      // velocity cells along the matching velocity axis
+    long nuz;        // length of a uz-line (scale granularity)
+    int V;           // adjacent inner elements per thread
+    int G;           // lanes per uz-line (scaled storage)
+    double shift[kMaxShiftTable];   // s_j = u_j dt a^-2 / dx per velocity index
+};
+
+// Velocity sweep along one velocity axis (Eq. 4).
+struct VelArgs {
+    const float* g;  // field component of this axis, [cells]
+    double factor;   // dt / du
+    int M;           // cells along the axis
+    long I;          // inner elements after the axis (1 for uz)
+    long nsub;       // ux: 1; uy: nux (sub-blocks per cell); uz: nux*nuy (lines per cell)
+    long nuz;
+    int V;
+    int G;
+    bool periodic;
+    double* outflow; // per spatial cell, or nullptr
+    double du3;
+    long cells;
+};
+
+hipError_t launch_position(int prec, const void* fin, const float* sin, void* fout, float* sout,
+                           const PosArgs& a, hipStream_t st);
+hipError_t launch_vel_strided(int prec, const void* fin, const float* sin, void* fout, float* sout,
+                              const VelArgs& a, hipStream_t st);
+hipError_t launch_vel_uz(int prec, const void* fin, const float* sin, void* fout, float* sout,
+                         const VelArgs& a, hipStream_t st);
+
+struct MomArgs {
+    long cells;
+    long Nu;
+    int nu[3];
+    double umin[3];  // -umax
+    double du[3];
+    double du3;
+    double* rho;
+    double* umean;   // [3][cells] or nullptr
+    long nuz;
+};
+hipError_t launch_moments(int prec, const void* f, const float* scale, const MomArgs& a,
+                          hipStream_t st);
+hipError_t launch_sum(const double* x, long n, double scale, double* out, hipStream_t st);
+
+}  // namespace vlasov

@@ -1,0 +1,278 @@
+"""Thin ctypes binding of libvlasov (the HIP library built from ``csrc/``).
+
+Each ``vlasov_*`` function has the name, argument order and meaning of the C
+entry point declared in ``include/vlasov.h``; this layer only marshals torch
+tensors (device memory) and the current HIP stream into pointers and turns a
+non-zero return code into ``VlasovError``.  All arithmetic runs in the HIP
+kernels.  The library must have been built (``python -m
+paper_2110_15867_amd.build``); importing this module without it raises.
+
+A few helpers (``new_state``, ``step``, ``moments``, ``advect``) allocate the
+output tensors with torch and call the entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvlasov.so")
+
+F32, F16, BF16 = 0, 1, 2
+VBC_OUTFLOW, VBC_PERIODIC = 0, 1
+TORCH_DTYPE = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
+PREC_NAME = {F32: "f32", F16: "f16", BF16: "bf16"}
+
+
+class VlasovError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {_lib.vlasov_strerror(code).decode()} (code {code})")
+        self.code = code
+
+
+class vlasov_grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("nu", ctypes.c_int32 * 3),
+                ("L", ctypes.c_double * 3), ("umax", ctypes.c_double * 3)]
+
+
+def make_grid(n, nu, L=(1.0, 1.0, 1.0), umax=(1.0, 1.0, 1.0)) -> vlasov_grid:
+    g = vlasov_grid()
+    for a in range(3):
+        g.n[a], g.nu[a] = int(n[a]), int(nu[a])
+        g.L[a], g.umax[a] = float(L[a]), float(umax[a])
+    return g
+
+
+def grid_shape(g: vlasov_grid):
+    return tuple(g.n) + tuple(g.nu)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2110_15867_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, D, I, S = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_size_t
+    G = ctypes.POINTER(vlasov_grid)
+    L.vlasov_abi_version.restype = I
+    L.vlasov_abi_version.argtypes = []
+    L.vlasov_strerror.restype = ctypes.c_char_p
+    L.vlasov_strerror.argtypes = [I]
+    L.vlasov_f_bytes.restype = S
+    L.vlasov_f_bytes.argtypes = [G, I]
+    L.vlasov_scale_bytes.restype = S
+    L.vlasov_scale_bytes.argtypes = [G, I]
+    for ax in "xyz":
+        fn = getattr(L, f"vlasov_advect_{ax}")
+        fn.restype = I
+        fn.argtypes = [G, I, P, P, P, P, D, P]
+        fn = getattr(L, f"vlasov_advect_u{ax}")
+        fn.restype = I
+        fn.argtypes = [G, I, I, P, P, P, P, P, D, P, P]
+    L.vlasov_step_workspace_bytes.restype = S
+    L.vlasov_step_workspace_bytes.argtypes = [G, I]
+    L.vlasov_step.restype = I
+    L.vlasov_step.argtypes = [G, I, I, P, P, P, P, P, P, D, D, P, S, P, P]
+    L.vlasov_moments.restype = I
+    L.vlasov_moments.argtypes = [G, I, P, P, P, P, P, P]
+    L.vlasov_sum_f64.restype = I
+    L.vlasov_sum_f64.argtypes = [P, ctypes.c_int64, P, P]
+    _bind_adjoint(L)
+    return L
+
+
+def _bind_adjoint(L):
+    P, D, I, S = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_size_t
+    G = ctypes.POINTER(vlasov_grid)
+    if not hasattr(L, "vlasov_step_adj"):
+        return
+    for ax in "xyz":
+        fn = getattr(L, f"vlasov_advect_{ax}_adj")
+        fn.restype = I
+        fn.argtypes = [G, P, P, P, D, P]
+        fn = getattr(L, f"vlasov_advect_u{ax}_adj")
+        fn.restype = I
+        fn.argtypes = [G, I, P, P, D, P, P, P, P]
+    L.vlasov_step_adj_workspace_bytes.restype = S
+    L.vlasov_step_adj_workspace_bytes.argtypes = [G]
+    L.vlasov_step_adj.restype = I
+    L.vlasov_step_adj.argtypes = [G, I, P, P, P, D, D, P, P, P, P, P, S, P]
+    L.vlasov_moments_adj.restype = I
+    L.vlasov_moments_adj.argtypes = [G, P, P, P, P, P]
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("libvlasov takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libvlasov takes contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise VlasovError(rc, what)
+
+
+# --- C entry points, same names -------------------------------------------------------
+
+def vlasov_abi_version() -> int:
+    return _lib.vlasov_abi_version()
+
+
+def vlasov_strerror(code: int) -> str:
+    return _lib.vlasov_strerror(code).decode()
+
+
+def vlasov_f_bytes(grid, prec) -> int:
+    return _lib.vlasov_f_bytes(ctypes.byref(grid), prec)
+
+
+def vlasov_scale_bytes(grid, prec) -> int:
+    return _lib.vlasov_scale_bytes(ctypes.byref(grid), prec)
+
+
+def _advect_pos(axis):
+    name = f"vlasov_advect_{axis}"
+
+    def fn(grid, prec, f_in, scale_in, f_out, scale_out, dt_over_a2, stream=None):
+        _check(getattr(_lib, name)(ctypes.byref(grid), prec, _ptr(f_in), _ptr(scale_in),
+                                   _ptr(f_out), _ptr(scale_out), float(dt_over_a2),
+                                   _stream(stream)), name)
+    fn.__name__ = name
+    return fn
+
+
+def _advect_vel(axis):
+    name = f"vlasov_advect_u{axis}"
+
+    def fn(grid, prec, vbc, f_in, scale_in, f_out, scale_out, g, dt, outflow=None, stream=None):
+        _check(getattr(_lib, name)(ctypes.byref(grid), prec, vbc, _ptr(f_in), _ptr(scale_in),
+                                   _ptr(f_out), _ptr(scale_out), _ptr(g), float(dt),
+                                   _ptr(outflow), _stream(stream)), name)
+    fn.__name__ = name
+    return fn
+
+
+vlasov_advect_x = _advect_pos("x")
+vlasov_advect_y = _advect_pos("y")
+vlasov_advect_z = _advect_pos("z")
+vlasov_advect_ux = _advect_vel("x")
+vlasov_advect_uy = _advect_vel("y")
+vlasov_advect_uz = _advect_vel("z")
+
+
+def vlasov_step_workspace_bytes(grid, prec) -> int:
+    return _lib.vlasov_step_workspace_bytes(ctypes.byref(grid), prec)
+
+
+def vlasov_step(grid, prec, vbc, f_in, scale_in, f_out, scale_out, g_n, g_np1, dt, a2inv,
+                work, work_bytes, outflow=None, stream=None):
+    _check(_lib.vlasov_step(ctypes.byref(grid), prec, vbc, _ptr(f_in), _ptr(scale_in),
+                            _ptr(f_out), _ptr(scale_out), _ptr(g_n), _ptr(g_np1), float(dt),
+                            float(a2inv), _ptr(work), int(work_bytes), _ptr(outflow),
+                            _stream(stream)), "vlasov_step")
+
+
+def vlasov_moments(grid, prec, f, scale, rho, umean, mass, stream=None):
+    _check(_lib.vlasov_moments(ctypes.byref(grid), prec, _ptr(f), _ptr(scale), _ptr(rho),
+                               _ptr(umean), _ptr(mass), _stream(stream)), "vlasov_moments")
+
+
+def vlasov_sum_f64(x, n, out, stream=None):
+    _check(_lib.vlasov_sum_f64(_ptr(x), int(n), _ptr(out), _stream(stream)), "vlasov_sum_f64")
+
+
+# --- convenience (allocation with torch, then the entry points) ----------------------------
+
+class State:
+    """f in one storage precision, with its scales for FP16/BF16."""
+
+    def __init__(self, grid, prec, f, scale=None):
+        self.grid, self.prec, self.f, self.scale = grid, prec, f, scale
+
+    @property
+    def shape(self):
+        return grid_shape(self.grid)
+
+
+def empty_state(grid, prec, device="cuda") -> State:
+    shape = grid_shape(grid)
+    f = torch.empty(shape, dtype=TORCH_DTYPE[prec], device=device)
+    scale = None
+    if prec != F32:
+        scale = torch.empty(shape[:-1], dtype=torch.float32, device=device)
+    return State(grid, prec, f, scale)
+
+
+def encode(grid, prec, f32) -> State:
+    """Store an FP32 tensor in the given precision (per-uz-line max scale, RNE codes).
+
+    This is input preparation with torch ops; the sweeps themselves requantise
+    inside the kernels.
+    """
+    if prec == F32:
+        return State(grid, prec, f32.contiguous())
+    scale = f32.abs().amax(dim=-1).contiguous()
+    inv = torch.where(scale > 0, 1.0 / scale, torch.zeros_like(scale))
+    codes = (f32 * inv[..., None]).to(TORCH_DTYPE[prec]).contiguous()
+    return State(grid, prec, codes, scale)
+
+
+def decode(state: State) -> torch.Tensor:
+    if state.prec == F32:
+        return state.f
+    return state.f.float() * state.scale[..., None]
+
+
+def advect(axis: str, state: State, dt, g=None, vbc=VBC_OUTFLOW, outflow=None, stream=None):
+    out = empty_state(state.grid, state.prec, state.f.device)
+    if axis in ("x", "y", "z"):
+        globals()[f"vlasov_advect_{axis}"](state.grid, state.prec, state.f, state.scale, out.f,
+                                          out.scale, dt, stream)
+    else:
+        globals()[f"vlasov_advect_{axis}"](state.grid, state.prec, vbc, state.f, state.scale,
+                                          out.f, out.scale, g, dt, outflow, stream)
+    return out
+
+
+def step(state: State, g_n, g_np1, dt, a2inv=1.0, vbc=VBC_OUTFLOW, outflow=None, work=None,
+         out=None, stream=None) -> State:
+    grid = state.grid
+    nbytes = vlasov_step_workspace_bytes(grid, state.prec)
+    if work is None:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=state.f.device)
+    if out is None:
+        out = empty_state(grid, state.prec, state.f.device)
+    vlasov_step(grid, state.prec, vbc, state.f, state.scale, out.f, out.scale, g_n, g_np1, dt,
+                a2inv, work, nbytes, outflow, stream)
+    return out
+
+
+def moments(state: State, with_mean=True, stream=None):
+    n = tuple(state.grid.n)
+    dev = state.f.device
+    rho = torch.empty(n, dtype=torch.float64, device=dev)
+    um = torch.empty((3,) + n, dtype=torch.float64, device=dev) if with_mean else None
+    mass = torch.empty((), dtype=torch.float64, device=dev)
+    vlasov_moments(state.grid, state.prec, state.f, state.scale, rho, um, mass, stream)
+    return rho, um, mass

@@ -1,0 +1,207 @@
+"""GPU parity: the HIP sweeps, step and moments against the FP64 oracle.
+
+Both sides start from the same float32 values (the oracle reads them as
+float64).  The bar for FP32 storage is the stated one: L-infinity difference
+at most 1e-5 of max f after each operator, total mass within 1e-6 relative.
+Shapes span several tiles and ragged tails (line lengths without a
+compile-time kernel, odd uz-lines, partial work-groups).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_15867_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs an MI355X", allow_module_level=True)
+
+from paper_2110_15867_amd import vlasov as V  # noqa: E402
+
+LINF = 1e-5
+
+
+def _grids():
+    return {
+        "ragged": dict(n=(6, 5, 7), nu=(12, 10, 9), L=(1.0, 0.8, 1.3), umax=(1.0, 1.2, 0.9)),
+        "tiny16": dict(n=(16, 16, 16), nu=(16, 16, 16), L=(1, 1, 1), umax=(1, 1, 1)),
+        "nu32": dict(n=(8, 6, 5), nu=(32, 32, 32), L=(1, 2, 10), umax=(1, 1, 1)),
+        "long64": dict(n=(64, 3, 64), nu=(4, 6, 64), L=(1, 1, 1), umax=(1, 1, 1)),
+        "odd_nuz": dict(n=(5, 4, 3), nu=(8, 6, 6), L=(1, 1, 1), umax=(1, 1, 1)),
+    }
+
+
+def _setup(name, seed=0):
+    d = _grids()[name]
+    og = oracle.Grid.make(d["n"], d["nu"], d["L"], d["umax"])
+    hg = V.make_grid(d["n"], d["nu"], d["L"], d["umax"])
+    rng = np.random.default_rng(100 + seed)
+    f32 = rng.uniform(0.0, 1.0, og.shape).astype(np.float32) ** 2
+    return og, hg, f32
+
+
+def _close(got, want, scale, tol=LINF):
+    err = np.max(np.abs(got.astype(np.float64) - want))
+    assert err <= tol * scale, f"max err {err:.3e} > {tol:.0e} * {scale:.3e}"
+    return err
+
+
+def _print_case(*parts):
+    print("case:", *parts, flush=True)
+
+
+@pytest.mark.parametrize("name", list(_grids()))
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("dt", [0.013, -0.21, 0.19, 2.7])
+def test_position_sweep_parity(name, axis, dt):
+    og, hg, f32 = _setup(name, axis)
+    _print_case("position", name, axis, dt)
+    want = oracle.advect_position(og, axis, f32.astype(np.float64), dt)
+    fin = torch.from_numpy(f32).cuda()
+    out = torch.empty_like(fin)
+    fn = [V.vlasov_advect_x, V.vlasov_advect_y, V.vlasov_advect_z][axis]
+    fn(hg, V.F32, fin, None, out, None, dt)
+    torch.cuda.synchronize()
+    _close(out.cpu().numpy(), want, float(f32.max()))
+
+
+@pytest.mark.parametrize("name", list(_grids()))
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("vbc", [0, 1])
+def test_velocity_sweep_parity(name, axis, vbc):
+    og, hg, f32 = _setup(name, 10 + axis)
+    _print_case("velocity", name, axis, vbc)
+    rng = np.random.default_rng(7 + axis)
+    cells = int(np.prod(og.n))
+    du = 2 * og.umax[axis] / og.nu[axis]
+    dt = 0.1
+    # shifts between -3.4 and 3.4 cells, including exact zeros and integers
+    s = rng.uniform(-3.4, 3.4, cells)
+    s[::7] = 0.0
+    s[3::11] = np.round(s[3::11])
+    field = np.zeros((3, cells), np.float32)
+    field[axis] = (s * du / dt).astype(np.float32)
+    field = field.reshape((3,) + tuple(og.n))
+    ofl_ref = np.zeros(cells)
+    want = oracle.advect_velocity(og, axis, f32.astype(np.float64), field, dt, vbc=vbc,
+                                  outflow=ofl_ref)
+    fin = torch.from_numpy(f32).cuda()
+    out = torch.empty_like(fin)
+    g = torch.from_numpy(field).cuda()
+    ofl = torch.zeros(tuple(og.n), dtype=torch.float64, device="cuda")
+    fn = [V.vlasov_advect_ux, V.vlasov_advect_uy, V.vlasov_advect_uz][axis]
+    fn(hg, V.F32, vbc, fin, None, out, None, g, dt, ofl)
+    torch.cuda.synchronize()
+    _close(out.cpu().numpy(), want, float(f32.max()))
+    du3 = np.prod([2 * og.umax[a] / og.nu[a] for a in range(3)])
+    lines = int(np.prod(og.nu)) // og.nu[axis]
+    np.testing.assert_allclose(ofl.cpu().numpy().reshape(-1), ofl_ref, rtol=1e-5,
+                               atol=1e-6 * float(f32.max()) * du3 * lines)
+
+
+@pytest.mark.parametrize("name", ["ragged", "nu32"])
+def test_integer_shifts_are_bit_exact(name):
+    og, hg, f32 = _setup(name, 3)
+    _print_case("integer", name)
+    fin = torch.from_numpy(f32).cuda()
+    out = torch.empty_like(fin)
+    # x: dt so that every s_j is an integer requires dx/du rational; use velocity sweeps
+    cells = int(np.prod(og.n))
+    for axis in range(3):
+        du = 2 * og.umax[axis] / og.nu[axis]
+        dt = 0.25
+        k = np.arange(cells) % 7 - 3
+        field = np.zeros((3, cells), np.float32)
+        field[axis] = (k * du / dt).astype(np.float32)
+        field = field.reshape((3,) + tuple(og.n))
+        want = oracle.advect_velocity(og, axis, f32.astype(np.float64), field, dt, vbc=1)
+        fn = [V.vlasov_advect_ux, V.vlasov_advect_uy, V.vlasov_advect_uz][axis]
+        fn(hg, V.F32, 1, fin, None, out, None, torch.from_numpy(field).cuda(), dt, None)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy().astype(np.float64), want)
+
+
+@pytest.mark.parametrize("k", [1])
+def test_step_parity_tiny_workload(k):
+    w = inputs.workload(k)
+    _print_case("step", w.name)
+    og = oracle.Grid.make(w.n, w.nu, w.L, w.umax)
+    hg = V.make_grid(w.n, w.nu, w.L, w.umax)
+    f32 = inputs.initial_f32(w)
+    pot = inputs.potential(w)
+    f_ref = f32.astype(np.float64)
+    st = V.State(hg, V.F32, torch.from_numpy(f32).cuda())
+    cells = int(np.prod(w.n))
+    ofl_ref = np.zeros(cells)
+    ofl = torch.zeros(tuple(w.n), dtype=torch.float64, device="cuda")
+    _, _, m0 = oracle.moments(og, f_ref)
+    for n in range(w.steps):
+        gn = inputs.accel_field(w, pot, n * w.dt)
+        gnp1 = inputs.accel_field(w, pot, (n + 1) * w.dt)
+        f_ref = oracle.step(og, f_ref, gn, gnp1, w.dt, outflow=ofl_ref)
+        st = V.step(st, torch.from_numpy(gn).cuda(), torch.from_numpy(gnp1).cuda(), w.dt,
+                    outflow=ofl)
+        torch.cuda.synchronize()
+        got = st.f.cpu().numpy()
+        _close(got, f_ref, float(f_ref.max()))
+        assert got.min() >= 0.0
+    rho, um, mass = V.moments(st)
+    rho_ref, um_ref, mass_ref = oracle.moments(og, f_ref)
+    assert float(mass) == pytest.approx(mass_ref, rel=1e-6)
+    dx3 = np.prod([w.L[a] / w.n[a] for a in range(3)])
+    # in-domain mass plus what left through the velocity faces is conserved
+    tot_out = float(ofl.sum()) * dx3
+    assert float(mass) + tot_out == pytest.approx(m0, rel=1e-6)
+    np.testing.assert_allclose(ofl.cpu().numpy().reshape(-1), ofl_ref, rtol=1e-4, atol=1e-9)
+
+
+@pytest.mark.parametrize("name", list(_grids()))
+def test_moments_parity(name):
+    og, hg, f32 = _setup(name, 5)
+    _print_case("moments", name)
+    rho_ref, um_ref, mass_ref = oracle.moments(og, f32.astype(np.float64))
+    st = V.State(hg, V.F32, torch.from_numpy(f32).cuda())
+    rho, um, mass = V.moments(st)
+    np.testing.assert_allclose(rho.cpu().numpy(), rho_ref, rtol=1e-12)
+    np.testing.assert_allclose(um.cpu().numpy(), um_ref, rtol=1e-10, atol=1e-13)
+    assert float(mass) == pytest.approx(mass_ref, rel=1e-12)
+
+
+def test_step_is_deterministic():
+    w = inputs.workload(1)
+    hg = V.make_grid(w.n, w.nu, w.L, w.umax)
+    f32 = torch.from_numpy(inputs.initial_f32(w)).cuda()
+    pot = inputs.potential(w)
+    gn = torch.from_numpy(inputs.accel_field(w, pot, 0.0)).cuda()
+    outs = []
+    for _ in range(2):
+        ofl = torch.zeros(tuple(w.n), dtype=torch.float64, device="cuda")
+        st = V.step(V.State(hg, V.F32, f32), gn, gn, w.dt, outflow=ofl)
+        rho, _, mass = V.moments(st)
+        outs.append((st.f.clone(), ofl.clone(), mass.clone()))
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1])
+    assert torch.equal(outs[0][2], outs[1][2])
+
+
+def test_argument_errors():
+    hg = V.make_grid((4, 4, 4), (8, 8, 8))
+    f = torch.zeros(V.grid_shape(hg), device="cuda")
+    with pytest.raises(V.VlasovError) as e:
+        V.vlasov_advect_x(hg, V.F32, f, None, f, None, 0.1)
+    assert e.value.code == -4
+    with pytest.raises(V.VlasovError) as e:
+        V.vlasov_advect_x(hg, 7, f, None, torch.empty_like(f), None, 0.1)
+    assert e.value.code == -3
+    with pytest.raises(V.VlasovError) as e:
+        V.vlasov_advect_x(hg, V.F32, f, None, torch.empty_like(f), None, float("nan"))
+    assert e.value.code == -5
+    with pytest.raises(V.VlasovError) as e:
+        V.vlasov_advect_x(hg, V.F16, f, None, torch.empty_like(f), None, 0.1)
+    assert e.value.code == -3
+    bad = V.make_grid((4, 0, 4), (8, 8, 8))
+    with pytest.raises(V.VlasovError) as e:
+        V.vlasov_advect_x(bad, V.F32, f, None, torch.empty_like(f), None, 0.1)
+    assert e.value.code == -2
