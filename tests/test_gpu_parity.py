@@ -107,14 +107,13 @@ def test_integer_shifts_are_bit_exact(name):
     _print_case("integer", name)
     fin = torch.from_numpy(f32).cuda()
     out = torch.empty_like(fin)
-    # x: dt so that every s_j is an integer requires dx/du rational; use velocity sweeps
     cells = int(np.prod(og.n))
     for axis in range(3):
         du = 2 * og.umax[axis] / og.nu[axis]
-        dt = 0.25
+        dt = 0.25 * du                     # dt/du = 1/4 exactly, so s = g/4 exactly
         k = np.arange(cells) % 7 - 3
         field = np.zeros((3, cells), np.float32)
-        field[axis] = (k * du / dt).astype(np.float32)
+        field[axis] = (4.0 * k).astype(np.float32)
         field = field.reshape((3,) + tuple(og.n))
         want = oracle.advect_velocity(og, axis, f32.astype(np.float64), field, dt, vbc=1)
         fn = [V.vlasov_advect_ux, V.vlasov_advect_uy, V.vlasov_advect_uz][axis]
