@@ -137,6 +137,19 @@ int vlasov_advect_uz(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc,
                      const void* f_in, const float* scale_in, void* f_out, float* scale_out,
                      const float* g, double dt, double* outflow, void* stream);
 
+/*
+ * Velocity kick: D_uz D_uy D_ux over dt with one field g, i.e. the three
+ * velocity sweeps of one half step of Eq. (5) (with dt the half step).
+ * The result is bitwise that of vlasov_advect_ux, _uy, _uz in sequence.
+ * Velocity blocks of 16^3 or 32^3 cells are swept inside LDS (one HBM read
+ * and one write of f instead of three); other shapes run the three sweeps
+ * and then need `work` (vlasov_step_workspace_bytes, else VLASOV_ERR_WORKSPACE);
+ * work may be NULL for the fused shapes.
+ */
+int vlasov_kick(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, const void* f_in,
+                const float* scale_in, void* f_out, float* scale_out, const float* g, double dt,
+                void* work, size_t work_bytes, double* outflow, void* stream);
+
 /* Bytes of workspace vlasov_step needs: one intermediate copy of f plus its
  * scales, 256-byte aligned. */
 size_t vlasov_step_workspace_bytes(const vlasov_grid* grid, vlasov_prec prec);
@@ -146,7 +159,8 @@ size_t vlasov_step_workspace_bytes(const vlasov_grid* grid, vlasov_prec prec);
  *   f^{n+1} = D_uz D_uy D_ux(dt/2; g_np1) D_x D_y D_z(dt) D_uz D_uy D_ux(dt/2; g_n) f^n
  * applied right to left: half kicks ux, uy, uz with the field at t^n, drifts
  * z, y, x with dt * a2inv, half kicks ux, uy, uz with the field at t^{n+1}.
- * Nine sweeps; intermediates ping-pong between f_out and work.
+ * Nine sweeps: each group of three velocity sweeps runs as one vlasov_kick;
+ * intermediates ping-pong between f_out and work.
  *   g_n, g_np1 : FP32 fields [3][nx][ny][nz] at t^n and t^{n+1}
  *   a2inv      : a(t)^-2 for the drifts
  *   work       : device workspace of at least vlasov_step_workspace_bytes
@@ -170,6 +184,12 @@ int vlasov_moments(const vlasov_grid* grid, vlasov_prec prec, const void* f, con
 /* Deterministic FP64 sum of x[0..n) into *out (device pointers): a single
  * work-group, fixed order.  Used for total mass and total outflow. */
 int vlasov_sum_f64(const double* x, int64_t n, double* out, void* stream);
+
+/* Plain copy of `bytes` (multiple of 16, 16-byte aligned, non-overlapping)
+ * from src to dst on the device: the HBM bandwidth probe that sets the
+ * practical ceiling of a streaming kernel and calibrates traffic counters.
+ * Not part of the method. */
+int vlasov_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

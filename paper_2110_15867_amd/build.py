@@ -2,7 +2,10 @@
 
 Every HIP source under csrc/ is compiled with hipcc for gfx950 and linked into
 ``libvlasov.so`` next to this file.  Packed FP32 instructions are disabled for
-all device code.  Run ``python -m paper_2110_15867_amd.build``.
+all device code, and the compiler may not contract a*b+c into a fused
+multiply-add on its own: the kernels write every FMA they want explicitly, so
+kernels that share the line arithmetic (single sweeps, the fused kick, the
+adjoints) round identically.  Run ``python -m paper_2110_15867_amd.build``.
 """
 from __future__ import annotations
 
@@ -23,7 +26,7 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     "-Wno-unused-function", "-Wno-unused-variable",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics",
+    "-ffp-contract=off",
 ]
 
 

@@ -154,6 +154,47 @@ int run_velocity(const vlasov_grid* g, const Dims& d, int axis, int prec, int vb
     return from_hip(launch_vel_strided(prec, fin, sin, fout, sout, a, st));
 }
 
+size_t lds_limit()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 0;
+    return (size_t)v;
+}
+
+// D_uz D_uy D_ux over dt with one field: fused in LDS where the velocity
+// block fits, otherwise three single sweeps through `mid` buffers.
+int run_kick(const vlasov_grid* g, const Dims& d, int prec, int vbc, const void* fin,
+             const float* sin, void* fout, float* sout, void* midf, float* mids,
+             const float* field, double dt, double* outflow, hipStream_t st)
+{
+    if (!isfinite(dt)) return VLASOV_ERR_NONFINITE;
+    int nu[3] = {(int)d.nu[0], (int)d.nu[1], (int)d.nu[2]};
+    if (kick_supported(nu, lds_limit())) {
+        KickArgs a;
+        memset(&a, 0, sizeof(a));
+        a.g = field;
+        for (int k = 0; k < 3; ++k) {
+            a.factor[k] = dt / (2.0 * g->umax[k] / g->nu[k]);
+            if (!isfinite(a.factor[k])) return VLASOV_ERR_NONFINITE;
+            a.nu[k] = nu[k];
+        }
+        a.periodic = vbc == VLASOV_VBC_PERIODIC;
+        a.outflow = outflow;
+        a.du3 = (2.0 * g->umax[0] / g->nu[0]) * (2.0 * g->umax[1] / g->nu[1]) *
+                (2.0 * g->umax[2] / g->nu[2]);
+        a.cells = d.cells;
+        return from_hip(launch_kick(prec, fin, sin, fout, sout, a, st));
+    }
+    if (midf == nullptr) return VLASOV_ERR_WORKSPACE;
+    int rc = run_velocity(g, d, 0, prec, vbc, fin, sin, fout, sout, field, dt, outflow, st);
+    if (rc) return rc;
+    rc = run_velocity(g, d, 1, prec, vbc, fout, sout, midf, mids, field, dt, outflow, st);
+    if (rc) return rc;
+    return run_velocity(g, d, 2, prec, vbc, midf, mids, fout, sout, field, dt, outflow, st);
+}
+
 int advect_position(const vlasov_grid* g, int axis, int prec, const void* fin, const float* sin,
                     void* fout, float* sout, double dt_over_a2, void* stream)
 {
@@ -293,35 +334,56 @@ int vlasov_step(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const vo
     hipStream_t st = (hipStream_t)stream;
     const double h = 0.5 * dt;
     const double dta = dt * a2inv;
-    // Eq. (5) right to left; buffers: in -> out -> work -> out -> ... -> out
-    struct Buf { const void* f; const float* s; };
-    Buf src{fin, sin};
-    void* dstf[2] = {fout, wf};
-    float* dsts[2] = {sout, ws};
-    int k = 0;
-    auto vel = [&](int axis, const float* field) {
-        const int r = run_velocity(g, d, axis, prec, vbc, src.f, src.s, dstf[k & 1], dsts[k & 1],
-                                   field, h, outflow, st);
-        src = Buf{dstf[k & 1], dsts[k & 1]};
-        ++k;
-        return r;
-    };
-    auto pos = [&](int axis) {
-        const int r = run_position(g, d, axis, prec, src.f, src.s, dstf[k & 1], dsts[k & 1], dta, st);
-        src = Buf{dstf[k & 1], dsts[k & 1]};
-        ++k;
-        return r;
-    };
-    if ((rc = vel(0, g_n))) return rc;
-    if ((rc = vel(1, g_n))) return rc;
-    if ((rc = vel(2, g_n))) return rc;
-    if ((rc = pos(2))) return rc;
-    if ((rc = pos(1))) return rc;
-    if ((rc = pos(0))) return rc;
-    if ((rc = vel(0, g_np1))) return rc;
-    if ((rc = vel(1, g_np1))) return rc;
-    if ((rc = vel(2, g_np1))) return rc;
-    return VLASOV_OK;
+    // Eq. (5) right to left: kick(g_n) -> z -> y -> x -> kick(g_np1).
+    // Buffers: in -> out (kick) -> work (z) -> out (y) -> work (x) -> out (kick);
+    // a kick that cannot run fused uses the other buffer as its middle stage.
+    if ((rc = run_kick(g, d, prec, vbc, fin, sin, fout, sout, wf, ws, g_n, h, outflow, st)))
+        return rc;
+    if ((rc = run_position(g, d, 2, prec, fout, sout, wf, ws, dta, st))) return rc;
+    if ((rc = run_position(g, d, 1, prec, wf, ws, fout, sout, dta, st))) return rc;
+    if ((rc = run_position(g, d, 0, prec, fout, sout, wf, ws, dta, st))) return rc;
+    if ((rc = run_kick(g, d, prec, vbc, wf, ws, fout, sout, nullptr, nullptr, g_np1, h, outflow,
+                       st)) == VLASOV_ERR_WORKSPACE) {
+        // unfused last kick: x result is in work; go work -> out -> work -> out
+        if ((rc = run_velocity(g, d, 0, prec, vbc, wf, ws, fout, sout, g_np1, h, outflow, st)))
+            return rc;
+        if ((rc = run_velocity(g, d, 1, prec, vbc, fout, sout, wf, ws, g_np1, h, outflow, st)))
+            return rc;
+        rc = run_velocity(g, d, 2, prec, vbc, wf, ws, fout, sout, g_np1, h, outflow, st);
+    }
+    return rc;
+}
+
+int vlasov_kick(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
+                const float* sin, void* fout, float* sout, const float* field, double dt,
+                void* work, size_t work_bytes, double* outflow, void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (vbc != VLASOV_VBC_OUTFLOW && vbc != VLASOV_VBC_PERIODIC) return VLASOV_ERR_PREC;
+    if (field == nullptr) return VLASOV_ERR_NULL;
+    int rc = check_io(d, prec, fin, sin, fout, sout);
+    if (rc) return rc;
+    const size_t fb = (size_t)d.total * elem_bytes(prec);
+    if (overlap(fout, fb, field, 3 * d.cells * sizeof(float))) return VLASOV_ERR_ALIAS;
+    if (outflow != nullptr && overlap(fout, fb, outflow, d.cells * sizeof(double)))
+        return VLASOV_ERR_ALIAS;
+    void* wf = nullptr;
+    float* ws = nullptr;
+    int nu[3] = {(int)d.nu[0], (int)d.nu[1], (int)d.nu[2]};
+    if (!kick_supported(nu, lds_limit())) {
+        const size_t need = vlasov_step_workspace_bytes(g, prec);
+        if (work == nullptr || work_bytes < need) return VLASOV_ERR_WORKSPACE;
+        const size_t sb = prec == VLASOV_F32 ? 0 : (size_t)(d.total / d.nu[2]) * sizeof(float);
+        if (overlap(work, need, fin, fb) || overlap(work, need, fout, fb) ||
+            overlap(work, need, sin, sb) || overlap(work, need, sout, sb))
+            return VLASOV_ERR_ALIAS;
+        wf = work;
+        ws = prec == VLASOV_F32 ? nullptr : (float*)((char*)work + align_up(fb));
+    }
+    return run_kick(g, d, prec, vbc, fin, sin, fout, sout, wf, ws, field, dt, outflow,
+                    (hipStream_t)stream);
 }
 
 int vlasov_moments(const vlasov_grid* g, vlasov_prec prec, const void* f, const float* scale,

@@ -45,6 +45,20 @@ hipError_t launch_vel_strided(int prec, const void* fin, const float* sin, void*
 hipError_t launch_vel_uz(int prec, const void* fin, const float* sin, void* fout, float* sout,
                          const VelArgs& a, hipStream_t st);
 
+// Fused kick: the three velocity sweeps of one half step (Eq. 5) in LDS.
+struct KickArgs {
+    const float* g;  // field [3][cells]
+    double factor[3];// dt / du per axis
+    bool periodic;
+    double* outflow;
+    double du3;
+    long cells;
+    int nu[3];
+};
+bool kick_supported(const int nu[3], size_t lds_limit);
+hipError_t launch_kick(int prec, const void* fin, const float* sin, void* fout, float* sout,
+                       const KickArgs& a, hipStream_t st);
+
 struct MomArgs {
     long cells;
     long Nu;

@@ -41,6 +41,20 @@ template <> struct Codec<PREC_BF16> {
 
 template <typename T, int V> struct alignas(sizeof(T) * V) Pack { T v[V]; };
 
+// Code of value x with inverse scale inv: the FP32 product, rounded once to
+// FP32, then rounded to the storage type.  The empty asm pins the FP32
+// product so instruction selection cannot merge the multiply into a
+// mixed-precision FMA with a single rounding; every kernel then encodes
+// identically.
+template <int P>
+__device__ __forceinline__ typename Codec<P>::T quantize(float x, float inv)
+{
+    if (!Codec<P>::scaled) return Codec<P>::enc(x);
+    float y = x * inv;
+    asm("" : "+v"(y));
+    return Codec<P>::enc(y);
+}
+
 template <int P, int V>
 __device__ __forceinline__ void load_row(const typename Codec<P>::T* p, float scale, float* x)
 {
@@ -56,7 +70,7 @@ __device__ __forceinline__ void store_row(typename Codec<P>::T* p, const float* 
     using T = typename Codec<P>::T;
     Pack<T, V> q;
 #pragma unroll
-    for (int v = 0; v < V; ++v) q.v[v] = Codec<P>::enc(Codec<P>::scaled ? x[v] * inv : x[v]);
+    for (int v = 0; v < V; ++v) q.v[v] = quantize<P>(x[v], inv);
     *reinterpret_cast<Pack<T, V>*>(p) = q;
 }
 

@@ -71,6 +71,8 @@ def _load():
         fn = getattr(L, f"vlasov_advect_u{ax}")
         fn.restype = I
         fn.argtypes = [G, I, I, P, P, P, P, P, D, P, P]
+    L.vlasov_kick.restype = I
+    L.vlasov_kick.argtypes = [G, I, I, P, P, P, P, P, D, P, S, P, P]
     L.vlasov_step_workspace_bytes.restype = S
     L.vlasov_step_workspace_bytes.argtypes = [G, I]
     L.vlasov_step.restype = I
@@ -79,6 +81,8 @@ def _load():
     L.vlasov_moments.argtypes = [G, I, P, P, P, P, P, P]
     L.vlasov_sum_f64.restype = I
     L.vlasov_sum_f64.argtypes = [P, ctypes.c_int64, P, P]
+    L.vlasov_stream_copy.restype = I
+    L.vlasov_stream_copy.argtypes = [P, P, S, P]
     _bind_adjoint(L)
     return L
 
@@ -181,6 +185,13 @@ vlasov_advect_uy = _advect_vel("y")
 vlasov_advect_uz = _advect_vel("z")
 
 
+def vlasov_kick(grid, prec, vbc, f_in, scale_in, f_out, scale_out, g, dt, work=None,
+                work_bytes=0, outflow=None, stream=None):
+    _check(_lib.vlasov_kick(ctypes.byref(grid), prec, vbc, _ptr(f_in), _ptr(scale_in),
+                            _ptr(f_out), _ptr(scale_out), _ptr(g), float(dt), _ptr(work),
+                            int(work_bytes), _ptr(outflow), _stream(stream)), "vlasov_kick")
+
+
 def vlasov_step_workspace_bytes(grid, prec) -> int:
     return _lib.vlasov_step_workspace_bytes(ctypes.byref(grid), prec)
 
@@ -200,6 +211,11 @@ def vlasov_moments(grid, prec, f, scale, rho, umean, mass, stream=None):
 
 def vlasov_sum_f64(x, n, out, stream=None):
     _check(_lib.vlasov_sum_f64(_ptr(x), int(n), _ptr(out), _stream(stream)), "vlasov_sum_f64")
+
+
+def vlasov_stream_copy(src, dst, nbytes, stream=None):
+    _check(_lib.vlasov_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)),
+           "vlasov_stream_copy")
 
 
 # --- convenience (allocation with torch, then the entry points) ----------------------------
@@ -252,6 +268,15 @@ def advect(axis: str, state: State, dt, g=None, vbc=VBC_OUTFLOW, outflow=None, s
     else:
         globals()[f"vlasov_advect_{axis}"](state.grid, state.prec, vbc, state.f, state.scale,
                                           out.f, out.scale, g, dt, outflow, stream)
+    return out
+
+
+def kick(state: State, g, dt, vbc=VBC_OUTFLOW, outflow=None, stream=None) -> State:
+    out = empty_state(state.grid, state.prec, state.f.device)
+    nbytes = vlasov_step_workspace_bytes(state.grid, state.prec)
+    work = torch.empty(nbytes, dtype=torch.uint8, device=state.f.device)
+    vlasov_kick(state.grid, state.prec, vbc, state.f, state.scale, out.f, out.scale, g, dt, work,
+                nbytes, outflow, stream)
     return out
 
 
