@@ -95,6 +95,25 @@ def lib():
         L.vor_moments.restype = ctypes.c_int
         L.vor_moments.argtypes = [ctypes.POINTER(Grid), c_double_p, c_double_p, c_double_p,
                                   c_double_p]
+        G = ctypes.POINTER(Grid)
+        D, I, Lg = ctypes.c_double, ctypes.c_int, ctypes.c_long
+        L.vor_sweep_line_jacobian.restype = None
+        L.vor_sweep_line_jacobian.argtypes = [c_double_p, Lg, D, I, I, c_double_p, c_double_p]
+        L.vor_advect_position_adj.restype = I
+        L.vor_advect_position_adj.argtypes = [G, I, c_double_p, c_double_p, c_double_p, D]
+        L.vor_advect_velocity_adj.restype = I
+        L.vor_advect_velocity_adj.argtypes = [G, I, I, c_double_p, c_float_p, D, c_double_p,
+                                              c_double_p, c_double_p]
+        L.vor_advect_velocity_tan.restype = I
+        L.vor_advect_velocity_tan.argtypes = [G, I, I, c_double_p, c_float_p, c_double_p, D,
+                                              c_double_p, c_double_p]
+        L.vor_advect_position_tan.restype = I
+        L.vor_advect_position_tan.argtypes = [G, I, c_double_p, c_double_p, c_double_p, D]
+        L.vor_step_adj.restype = I
+        L.vor_step_adj.argtypes = [G, I, c_double_p, c_float_p, c_float_p, D, D, c_double_p,
+                                   c_double_p, c_double_p, c_double_p]
+        L.vor_moments_adj.restype = I
+        L.vor_moments_adj.argtypes = [G, c_double_p, c_double_p, c_double_p, c_double_p]
         _lib = L
     return _lib
 
@@ -208,3 +227,78 @@ def moments(grid: Grid, f):
     _check(lib().vor_moments(ctypes.byref(grid), _dp(f), _dp(rho), _dp(um), ctypes.byref(mass)),
            "moments")
     return rho.reshape(tuple(grid.n)), um.reshape((3,) + tuple(grid.n)), mass.value
+
+
+# --- derivatives (frozen limiter selections) ----------------------------------------
+
+def sweep_line_jacobian(line, s, periodic=True, limiter=True):
+    """(J, dnu): d out / d f (M x M) and d out / d nu of one line sweep."""
+    line = _f64(line)
+    M = line.size
+    J = np.zeros((M, M))
+    dn = np.zeros(M)
+    lib().vor_sweep_line_jacobian(_dp(line), M, float(s), int(periodic), int(limiter), _dp(J),
+                                  _dp(dn))
+    return J, dn
+
+
+def advect_position_adj(grid, axis, f, lam_out, dt_over_a2):
+    f, lam_out = _f64(f), _f64(lam_out)
+    out = np.empty_like(f)
+    _check(lib().vor_advect_position_adj(ctypes.byref(grid), axis, _dp(f), _dp(lam_out),
+                                         _dp(out), dt_over_a2), "advect_position_adj")
+    return out
+
+
+def advect_position_tan(grid, axis, f, v, dt_over_a2):
+    f, v = _f64(f), _f64(v)
+    out = np.empty_like(f)
+    _check(lib().vor_advect_position_tan(ctypes.byref(grid), axis, _dp(f), _dp(v), _dp(out),
+                                         dt_over_a2), "advect_position_tan")
+    return out
+
+
+def advect_velocity_adj(grid, axis, f, g, dt, lam_out, vbc=0, lam_g=None):
+    """Returns lam_in; lam_g (float64 [3, cells]) is accumulated in place if given."""
+    f, lam_out = _f64(f), _f64(lam_out)
+    g = np.ascontiguousarray(g, dtype=np.float32)
+    out = np.empty_like(f)
+    _check(lib().vor_advect_velocity_adj(ctypes.byref(grid), axis, vbc, _dp(f), _fp(g), dt,
+                                         _dp(lam_out), _dp(out), _dp(lam_g)),
+           "advect_velocity_adj")
+    return out
+
+
+def advect_velocity_tan(grid, axis, f, g, dt, v, g_dot=None, vbc=0):
+    f, v = _f64(f), _f64(v)
+    g = np.ascontiguousarray(g, dtype=np.float32)
+    gd = None if g_dot is None else _f64(g_dot)
+    out = np.empty_like(f)
+    _check(lib().vor_advect_velocity_tan(ctypes.byref(grid), axis, vbc, _dp(f), _fp(g), _dp(gd),
+                                         dt, _dp(v), _dp(out)), "advect_velocity_tan")
+    return out
+
+
+def step_adj(grid, f, g_n, g_np1, dt, lam_out, a2inv=1.0, vbc=0, lam_g_n=None, lam_g_np1=None):
+    """Adjoint of one Strang step; returns lam_in, accumulates lam_g_n / lam_g_np1."""
+    f, lam_out = _f64(f), _f64(lam_out)
+    cells = grid.n[0] * grid.n[1] * grid.n[2]
+    if lam_g_n is None:
+        lam_g_n = np.zeros(3 * cells)
+    if lam_g_np1 is None:
+        lam_g_np1 = np.zeros(3 * cells)
+    out = np.empty_like(f)
+    _check(lib().vor_step_adj(ctypes.byref(grid), vbc, _dp(f),
+                              _fp(np.ascontiguousarray(g_n, np.float32)),
+                              _fp(np.ascontiguousarray(g_np1, np.float32)), dt, a2inv,
+                              _dp(lam_out), _dp(out), _dp(lam_g_n), _dp(lam_g_np1)), "step_adj")
+    return out
+
+
+def moments_adj(grid, f, lam_rho, lam_umean=None):
+    f = _f64(f)
+    out = np.zeros_like(f)
+    _check(lib().vor_moments_adj(ctypes.byref(grid), _dp(f), _dp(_f64(lam_rho)),
+                                 _dp(None if lam_umean is None else _f64(lam_umean)), _dp(out)),
+           "moments_adj")
+    return out

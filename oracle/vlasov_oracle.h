@@ -40,6 +40,29 @@ int vor_step(const vor_grid* g, int vbc, const double* fin, double* fout, double
              const float* g_n, const float* g_np1, double dt, double a2inv, double* outflow);
 int vor_moments(const vor_grid* g, const double* f, double* rho, double* umean, double* mass);
 
+/* derivatives (vlasov_oracle_adj.c) */
+void vor_sweep_line_jacobian(const double* f, long M, double s, int periodic, int limiter,
+                             double* J, double* dnu);
+void vor_sweep_line_tangent(const double* f, long M, double s, int periodic, const double* v,
+                            double nu_dot, double* out_dot);
+void vor_sweep_line_adjoint(const double* f, long M, double s, int periodic, const double* lam,
+                            double* lam_in, double* lam_nu);
+int vor_advect_position_adj(const vor_grid* g, int a, const double* fin, const double* lam_out,
+                            double* lam_in, double dt_over_a2);
+int vor_advect_velocity_adj(const vor_grid* g, int a, int vbc, const double* fin,
+                            const float* gfield, double dt, const double* lam_out,
+                            double* lam_in, double* lam_g);
+int vor_advect_velocity_tan(const vor_grid* g, int a, int vbc, const double* fin,
+                            const float* gfield, const double* g_dot, double dt, const double* v,
+                            double* out_dot);
+int vor_advect_position_tan(const vor_grid* g, int a, const double* fin, const double* v,
+                            double* out_dot, double dt_over_a2);
+int vor_step_adj(const vor_grid* g, int vbc, const double* fin, const float* g_n,
+                 const float* g_np1, double dt, double a2inv, const double* lam_out,
+                 double* lam_in, double* lam_g_n, double* lam_g_np1);
+int vor_moments_adj(const vor_grid* g, const double* f, const double* lam_rho,
+                    const double* lam_umean, double* lam_f);
+
 #ifdef __cplusplus
 }
 #endif

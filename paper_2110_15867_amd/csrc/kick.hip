@@ -24,17 +24,21 @@
 
 namespace vlasov {
 
-// Round one sweep's outputs as storage would: the uz-line scale is the
-// largest |value|, values become code * scale.  For lines along ux or uy the
-// NZ values of a uz-line sit in NZ consecutive lanes (aligned groups).
-template <int P>
-__device__ __forceinline__ float storage_round_group(float x, int group)
+// Round the uz-line held by this thread in LDS as storage would: its scale
+// is the largest |value|, each value becomes code * scale.
+template <int P, int NZ>
+__device__ __forceinline__ void storage_round_line(float* line)
 {
-    if (!Codec<P>::scaled) return x;
-    float m = fabsf(x);
-    for (int w = 1; w < group; w <<= 1) m = fmaxf(m, __shfl_xor(m, w));
+    float x[NZ];
+    float m = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+        x[i] = line[i];
+        m = fmaxf(m, fabsf(x[i]));
+    }
     const float inv = m > 0.0f ? 1.0f / m : 0.0f;
-    return Codec<P>::dec(quantize<P>(x, inv)) * m;
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) line[i] = Codec<P>::dec(quantize<P>(x[i], inv)) * m;
 }
 
 template <int P, int NX, int NY, int NZ>
@@ -94,9 +98,10 @@ __global__ void __launch_bounds__(NY * NZ) k_kick(const typename Codec<P>::T* __
         __syncthreads();            // every line read before any is overwritten
         if (axis < 2) {
 #pragma unroll
-            for (int i = 0; i < NX; ++i) {
-                const int p = dir > 0 ? i : NX - 1 - i;
-                lds[base + p * stride] = storage_round_group<P>(wr.out[i], NZ);
+            for (int i = 0; i < NX; ++i) lds[base + (dir > 0 ? i : NX - 1 - i) * stride] = wr.out[i];
+            if (Codec<P>::scaled) {
+                __syncthreads();
+                storage_round_line<P, NZ>(lds + t * LS);
             }
         } else {
             float inv = 1.0f;

@@ -4,8 +4,7 @@
 //
 // All flux arithmetic is FP32 (section 5.1.1).  Each walker streams one line
 // (or V lines side by side) through a register window, so every cell is
-// loaded once, every interface flux is evaluated once, and every curvature
-// and curvature-minmod is computed once and reused by its neighbours.
+// loaded once and every interface flux is evaluated once.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -122,9 +121,8 @@ __device__ __forceinline__ LineShift split_shift(double s, int M, bool periodic)
 
 // ---------------------------------------------------------------------------
 // Suresh-Huynh monotonicity-preserving bounds (alpha = 4, epsilon = 0) and the
-// positivity clamp, for one interface in its upwind frame.  a..e are the cell
-// averages j-2..j+2 (j = upwind cell); Mp and Mm are the curvature minmods at
-// j+1/2 and j-1/2.  Returns the flux magnitude through the interface.
+// positivity clamp, for one interface in its upwind frame; a..e are the cell
+// averages j-2..j+2 (j = upwind cell).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float med3(float a, float b, float c)
 {
@@ -147,26 +145,93 @@ __device__ __forceinline__ float curvature(float l, float c, float r)
     return fmaf(-2.0f, c, l + r);
 }
 
-__device__ __forceinline__ float flux_mag(float a, float b, float c, float d, float e, float Mp,
-                                          float Mm, const LineShift& sh)
+// Upwind-frame stencil of one interface j+1/2: cell averages a..e =
+// f_{j-2..j+2} and their differences b-a, c-b, d-c, e-d.  The walkers carry
+// the differences from interface to interface, so each costs one subtraction.
+struct Stencil {
+    float a, b, c, d, e;
+    float dm2, dm1, d0, dp1;
+};
+
+// The bounded value median(fhat, fmin, fmax) of the Suresh-Huynh constraint.
+__device__ __forceinline__ float mp_bounded(float fhat, const Stencil& s)
 {
-    // unlimited SL interface value
-    float fhat = sh.w0 * a;
-    fhat = fmaf(sh.w1, b, fhat);
-    fhat = fmaf(sh.w2, c, fhat);
-    fhat = fmaf(sh.w3, d, fhat);
-    fhat = fmaf(sh.w4, e, fhat);
-    // bounds
-    const float cb = c - b;
-    const float fUL = fmaf(4.0f, cb, c);
-    const float fMD = 0.5f * ((c + d) - Mp);
-    const float fLC = fmaf(4.0f / 3.0f, Mm, fmaf(0.5f, cb, c));
-    const float lo = fmaxf(fminf(fminf(c, d), fMD), fminf(fminf(c, fUL), fLC));
-    const float hi = fminf(fmaxf(fmaxf(c, d), fMD), fmaxf(fmaxf(c, fUL), fLC));
-    const float lim = med3(fhat, lo, hi);
-    // positivity: what leaves the upwind cell lies between 0 and its content
-    return med3(sh.mu * lim, 0.0f, c);
+    const float Dm = s.dm1 - s.dm2;                 // curvature at j-1
+    const float D0 = s.d0 - s.dm1;                  // curvature at j
+    const float Dp = s.dp1 - s.d0;                  // curvature at j+1
+    const float Mp = curv_minmod(D0, Dp);           // d^M4 at j+1/2
+    const float Mm = curv_minmod(Dm, D0);           // d^M4 at j-1/2
+    const float fUL = fmaf(4.0f, s.dm1, s.c);
+    const float fMD = 0.5f * ((s.c + s.d) - Mp);
+    const float fLC = fmaf(4.0f / 3.0f, Mm, fmaf(0.5f, s.dm1, s.c));
+    const float lo = fmaxf(fminf(fminf(s.c, s.d), fMD), fminf(fminf(s.c, fUL), fLC));
+    const float hi = fminf(fmaxf(fmaxf(s.c, s.d), fMD), fmaxf(fmaxf(s.c, fUL), fLC));
+    return med3(fhat, lo, hi);
 }
+
+// Flux magnitude through the interface j+1/2 in its upwind frame: the SL
+// interface value, limited, times mu, clamped to [0, c].
+// Suresh & Huynh keep the unlimited value when it lies between f_j and
+// f_MP = f_j + minmod(f_{j+1} - f_j, alpha (f_j - f_{j-1})); that interval
+// lies inside [fmin, fmax], so with epsilon = 0 the test only skips work:
+// the curvatures and bounds are evaluated for the (rarer, and in smooth data
+// wave-coherent) interfaces that fail it.
+__device__ __forceinline__ float flux_mag(const Stencil& s, const LineShift& sh)
+{
+    float fhat = sh.w0 * s.a;
+    fhat = fmaf(sh.w1, s.b, fhat);
+    fhat = fmaf(sh.w2, s.c, fhat);
+    fhat = fmaf(sh.w3, s.d, fhat);
+    fhat = fmaf(sh.w4, s.e, fhat);
+    const float m = med3(s.d0, 4.0f * s.dm1, 0.0f);     // f_MP - f_j
+    const float y = fhat - s.c;
+    float lim = fhat;
+    if (__builtin_expect(med3(y, 0.0f, m) != y, 0)) lim = mp_bounded(fhat, s);
+    // positivity: what leaves the upwind cell lies between 0 and its content
+    return med3(sh.mu * lim, 0.0f, s.c);
+}
+
+// ---------------------------------------------------------------------------
+// Read-ahead of a line: keeps PD rows in flight in a register ring so that
+// the loads of later rows overlap the flux arithmetic of earlier ones.  Rows
+// are fetched from the wrapped reader in order and never beyond `total`.
+// (PD = 1 is a plain pass-through, used when the line length is not known at
+// compile time and a register ring could not be indexed statically.)
+// ---------------------------------------------------------------------------
+template <int V, int PD, class Reader>
+struct ReadAhead {
+    Reader& rd;
+    float ring[PD][V];
+    int head;
+    int fetched;
+    int total;
+
+    __device__ ReadAhead(Reader& r, int tot) : rd(r), head(0), fetched(0), total(tot)
+    {
+#pragma unroll
+        for (int k = 0; k < PD; ++k) {
+            if (fetched < total) {
+                rd.next(ring[k]);
+                ++fetched;
+            }
+        }
+    }
+    __device__ void next(float* x)
+    {
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[v] = ring[head][v];
+        if (fetched < total) {
+            rd.next(ring[head]);
+            ++fetched;
+        }
+        head = head + 1 == PD ? 0 : head + 1;
+    }
+};
+
+template <int V, int MT>
+struct ReadAheadDepth {
+    static constexpr int value = 1;
+};
 
 // ---------------------------------------------------------------------------
 // Uniform walker: every lane of the wave moves in the same direction, so the
@@ -186,13 +251,14 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
 {
     const int M = MT > 0 ? MT : Mrt;
     const int N = sh.N;
-    float xm2[V], xm1[V], x0[V], xp1[V], xp2[V];
-    float Dm1[V], D0[V], Dp1[V], Mm[V], phi_old[V];
+    float xm2[V], xm1[V], x0[V], xp1[V], xp2[V], phi_old[V];
+    float dm2[V], dm1[V], d0[V], dp1[V];    // x_{j-1}-x_{j-2}, ..., x_{j+2}-x_{j+1}
     float head[5][V];
     float acc = 0.0f;
     int r = -N - 3;                       // frame row of the next value
     rd.seek(r);
-    rd.next(xm2); rd.next(xm1); rd.next(x0); rd.next(xp1); rd.next(xp2);
+    ReadAhead<V, ReadAheadDepth<V, MT>::value, Reader> ra(rd, (MT > 0 && periodic) ? M : M + 5);
+    ra.next(xm2); ra.next(xm1); ra.next(x0); ra.next(xp1); ra.next(xp2);
     if (!periodic) {
         // rows already in the window that lie past the upper face
 #pragma unroll
@@ -213,19 +279,17 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
         }
     }
     r += 5;
-    // state for the interface (j0-1)+1/2, j0 = -N
+    // flux through (j0-1)+1/2, j0 = -N; then slide the window to j0
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        Dm1[v] = curvature(xm2[v], xm1[v], x0[v]);
-        D0[v] = curvature(xm1[v], x0[v], xp1[v]);
-        Dp1[v] = curvature(x0[v], xp1[v], xp2[v]);
-        Mm[v] = curv_minmod(Dm1[v], D0[v]);
-        const float Mp = curv_minmod(D0[v], Dp1[v]);
-        phi_old[v] = flux_mag(xm2[v], xm1[v], x0[v], xp1[v], xp2[v], Mp, Mm[v], sh);
-        Mm[v] = Mp;
-        // slide by one: window for j0
+        dm2[v] = xm1[v] - xm2[v];
+        dm1[v] = x0[v] - xm1[v];
+        d0[v] = xp1[v] - x0[v];
+        dp1[v] = xp2[v] - xp1[v];
+        phi_old[v] = flux_mag(Stencil{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v], dm1[v], d0[v],
+                                      dp1[v]}, sh);
         xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v];
-        Dm1[v] = D0[v]; D0[v] = Dp1[v];
+        dm2[v] = dm1[v]; dm1[v] = d0[v]; d0[v] = dp1[v];
     }
 #pragma unroll(MT > 0 ? MT : 1)
     for (int i = 0; i < M; ++i) {
@@ -234,7 +298,7 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
 #pragma unroll
             for (int v = 0; v < V; ++v) xp2[v] = head[i - (M - 5)][v];
         } else {
-            rd.next(xp2);
+            ra.next(xp2);
         }
         if (!periodic) {
             if (r >= M - N && r < M) {
@@ -246,14 +310,13 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
         float res[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            Dp1[v] = curvature(x0[v], xp1[v], xp2[v]);
-            const float Mp = curv_minmod(D0[v], Dp1[v]);
-            const float phi = flux_mag(xm2[v], xm1[v], x0[v], xp1[v], xp2[v], Mp, Mm[v], sh);
+            dp1[v] = xp2[v] - xp1[v];
+            const float phi = flux_mag(Stencil{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v],
+                                               dm1[v], d0[v], dp1[v]}, sh);
             res[v] = x0[v] - (phi - phi_old[v]);
             phi_old[v] = phi;
-            Mm[v] = Mp;
             xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v];
-            Dm1[v] = D0[v]; D0[v] = Dp1[v];
+            dm2[v] = dm1[v]; dm1[v] = d0[v]; d0[v] = dp1[v];
         }
         wr.put(i, res);
     }
@@ -274,11 +337,31 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
     }
 }
 
+// Upwind stencil of the interface j+1/2 from the window x_{j-2..j+3} and its
+// differences: as is for a rightward shift, mirrored (x_{j+3..j-1}, negated
+// differences in reverse order) for a leftward one.
+__device__ __forceinline__ Stencil mixed_stencil(bool neg, float xm2, float xm1, float x0, float xp1,
+                                                 float xp2, float xp3, float q0, float q1,
+                                                 float q2, float q3, float q4)
+{
+    Stencil s;
+    s.a = neg ? xp3 : xm2;
+    s.b = neg ? xp2 : xm1;
+    s.c = neg ? xp1 : x0;
+    s.d = neg ? x0 : xp1;
+    s.e = neg ? xm1 : xp2;
+    s.dm2 = neg ? -q4 : q0;
+    s.dm1 = neg ? -q3 : q1;
+    s.d0 = neg ? -q2 : q2;
+    s.dp1 = neg ? -q1 : q3;
+    return s;
+}
+
 // ---------------------------------------------------------------------------
 // Mixed walker: lanes of one wave may move in opposite directions (the z
 // sweep, where the shift follows the contiguous u_z index).  All lanes walk
-// forward with a 6-cell window; each lane picks its upwind stencil and the
-// matching curvature minmod by select.  Periodic lines only.
+// forward with a 6-cell window; each lane picks its upwind stencil by select.
+// Periodic lines only.
 // ---------------------------------------------------------------------------
 template <int V, int MT, class Reader, class Writer>
 __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt, const int Nsgn,
@@ -286,13 +369,13 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
 {
     const int M = MT > 0 ? MT : Mrt;
     const bool neg = sh.neg;
-    // signed integer offset in the physical frame: out_i = x_{i-Ns} ...
-    const int Ns = Nsgn;
-    float xm2[V], xm1[V], x0[V], xp1[V], xp2[V], xp3[V];
-    float Dm1[V], D0[V], Dp1[V], Dp2[V], Mm[V], M0[V], phi_old[V];
+    const int Ns = Nsgn;                  // out_i = x_{i-Ns} - (Phi_{i-Ns+1/2} - Phi_{i-Ns-1/2})
+    float xm2[V], xm1[V], x0[V], xp1[V], xp2[V], xp3[V], phi_old[V];
+    float q0[V], q1[V], q2[V], q3[V], q4[V];   // x_{j-1}-x_{j-2}, ..., x_{j+3}-x_{j+2}
     float head[6][V];
     rd.seek(-Ns - 3);
-    rd.next(xm2); rd.next(xm1); rd.next(x0); rd.next(xp1); rd.next(xp2); rd.next(xp3);
+    ReadAhead<V, ReadAheadDepth<V, MT>::value, Reader> ra(rd, MT > 0 ? M : M + 6);
+    ra.next(xm2); ra.next(xm1); ra.next(x0); ra.next(xp1); ra.next(xp2); ra.next(xp3);
     if (MT > 0) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -300,25 +383,18 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
             head[3][v] = xp1[v]; head[4][v] = xp2[v]; head[5][v] = xp3[v];
         }
     }
-    // state for j = j0 - 1
+    // flux through (j0-1)+1/2, then slide
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        Dm1[v] = curvature(xm2[v], xm1[v], x0[v]);
-        D0[v] = curvature(xm1[v], x0[v], xp1[v]);
-        Dp1[v] = curvature(x0[v], xp1[v], xp2[v]);
-        Dp2[v] = curvature(xp1[v], xp2[v], xp3[v]);
-        Mm[v] = curv_minmod(Dm1[v], D0[v]);
-        M0[v] = curv_minmod(D0[v], Dp1[v]);
-        const float Mp = curv_minmod(Dp1[v], Dp2[v]);
-        const float a = neg ? xp3[v] : xm2[v];
-        const float b = neg ? xp2[v] : xm1[v];
-        const float c = neg ? xp1[v] : x0[v];
-        const float d = neg ? x0[v] : xp1[v];
-        const float e = neg ? xm1[v] : xp2[v];
-        phi_old[v] = flux_mag(a, b, c, d, e, M0[v], neg ? Mp : Mm[v], sh);
-        Mm[v] = M0[v]; M0[v] = Mp;
+        q0[v] = xm1[v] - xm2[v];
+        q1[v] = x0[v] - xm1[v];
+        q2[v] = xp1[v] - x0[v];
+        q3[v] = xp2[v] - xp1[v];
+        q4[v] = xp3[v] - xp2[v];
+        phi_old[v] = flux_mag(mixed_stencil(neg, xm2[v], xm1[v], x0[v], xp1[v], xp2[v], xp3[v],
+                                            q0[v], q1[v], q2[v], q3[v], q4[v]), sh);
         xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v]; xp2[v] = xp3[v];
-        Dm1[v] = D0[v]; D0[v] = Dp1[v]; Dp1[v] = Dp2[v];
+        q0[v] = q1[v]; q1[v] = q2[v]; q2[v] = q3[v]; q3[v] = q4[v];
     }
     const float sgn = neg ? -1.0f : 1.0f;
 #pragma unroll(MT > 0 ? MT : 1)
@@ -327,24 +403,19 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
 #pragma unroll
             for (int v = 0; v < V; ++v) xp3[v] = head[i - (M - 6)][v];
         } else {
-            rd.next(xp3);
+            ra.next(xp3);
         }
         float res[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            Dp2[v] = curvature(xp1[v], xp2[v], xp3[v]);
-            const float Mp = curv_minmod(Dp1[v], Dp2[v]);
-            const float a = neg ? xp3[v] : xm2[v];
-            const float b = neg ? xp2[v] : xm1[v];
-            const float c = neg ? xp1[v] : x0[v];
-            const float d = neg ? x0[v] : xp1[v];
-            const float e = neg ? xm1[v] : xp2[v];
-            const float phi = flux_mag(a, b, c, d, e, M0[v], neg ? Mp : Mm[v], sh);
+            q4[v] = xp3[v] - xp2[v];
+            const float phi = flux_mag(mixed_stencil(neg, xm2[v], xm1[v], x0[v], xp1[v], xp2[v],
+                                                     xp3[v], q0[v], q1[v], q2[v], q3[v], q4[v]),
+                                       sh);
             res[v] = fmaf(-sgn, phi - phi_old[v], x0[v]);
             phi_old[v] = phi;
-            Mm[v] = M0[v]; M0[v] = Mp;
             xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v]; xp2[v] = xp3[v];
-            Dm1[v] = D0[v]; D0[v] = Dp1[v]; Dp1[v] = Dp2[v];
+            q0[v] = q1[v]; q1[v] = q2[v]; q2[v] = q3[v]; q3[v] = q4[v];
         }
         wr.put(i, res);
     }
