@@ -181,6 +181,83 @@ int vlasov_step(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, const
 int vlasov_moments(const vlasov_grid* grid, vlasov_prec prec, const void* f, const float* scale,
                    double* rho, double* umean, double* mass, void* stream);
 
+/*
+ * Derivatives (FP32 storage only).  With the limiter's selections frozen at
+ * the forward input f_in -- the forward arithmetic is re-run on f_in and each
+ * minimum, maximum, median, minmod and clamp keeps the argument it selected
+ * -- a sweep is the linear map f_out = J f_in, smooth in the fractional
+ * shift.  At ties between equal candidates the first argument of a minimum
+ * or maximum wins and the median is max(min(x,y), min(max(x,y),z)); at a
+ * whole-cell shift the shift derivative is the one-sided limit from the side
+ * the shift comes from.  Tangent and adjoint share one linearisation, so
+ * <tan(v), w> = <v, adj(w)> (+ field terms) up to FP32 rounding.
+ *
+ *   _tan: v_out = J v_in (+ d f_out/d g . g_dot for velocity sweeps; g_dot
+ *         is FP32 [3][cells] or NULL; only the swept component is read)
+ *   _adj: lam_in = J^T lam_out (overwritten); velocity sweeps ADD
+ *         lam_out . d f_out/d g to lam_g[axis][cell] (FP32 [3][cells], or
+ *         NULL to skip)
+ * All arrays are device FP32 in the layout of f; outputs must not overlap
+ * the inputs.
+ */
+int vlasov_advect_x_tan(const vlasov_grid* grid, const float* f_in, const float* v_in,
+                        float* v_out, double dt_over_a2, void* stream);
+int vlasov_advect_y_tan(const vlasov_grid* grid, const float* f_in, const float* v_in,
+                        float* v_out, double dt_over_a2, void* stream);
+int vlasov_advect_z_tan(const vlasov_grid* grid, const float* f_in, const float* v_in,
+                        float* v_out, double dt_over_a2, void* stream);
+int vlasov_advect_x_adj(const vlasov_grid* grid, const float* f_in, const float* lam_out,
+                        float* lam_in, double dt_over_a2, void* stream);
+int vlasov_advect_y_adj(const vlasov_grid* grid, const float* f_in, const float* lam_out,
+                        float* lam_in, double dt_over_a2, void* stream);
+int vlasov_advect_z_adj(const vlasov_grid* grid, const float* f_in, const float* lam_out,
+                        float* lam_in, double dt_over_a2, void* stream);
+int vlasov_advect_ux_tan(const vlasov_grid* grid, vlasov_vbc vbc, const float* f_in,
+                         const float* g, const float* g_dot, double dt, const float* v_in,
+                         float* v_out, void* stream);
+int vlasov_advect_uy_tan(const vlasov_grid* grid, vlasov_vbc vbc, const float* f_in,
+                         const float* g, const float* g_dot, double dt, const float* v_in,
+                         float* v_out, void* stream);
+int vlasov_advect_uz_tan(const vlasov_grid* grid, vlasov_vbc vbc, const float* f_in,
+                         const float* g, const float* g_dot, double dt, const float* v_in,
+                         float* v_out, void* stream);
+int vlasov_advect_ux_adj(const vlasov_grid* grid, vlasov_vbc vbc, const float* f_in,
+                         const float* g, double dt, const float* lam_out, float* lam_in,
+                         float* lam_g, void* stream);
+int vlasov_advect_uy_adj(const vlasov_grid* grid, vlasov_vbc vbc, const float* f_in,
+                         const float* g, double dt, const float* lam_out, float* lam_in,
+                         float* lam_g, void* stream);
+int vlasov_advect_uz_adj(const vlasov_grid* grid, vlasov_vbc vbc, const float* f_in,
+                         const float* g, double dt, const float* lam_out, float* lam_in,
+                         float* lam_g, void* stream);
+
+/* Workspace of vlasov_step_adj: the eight intermediate stages of Eq. (5)
+ * recomputed from f_in plus one adjoint buffer (nine FP32 copies of f). */
+size_t vlasov_step_adj_workspace_bytes(const vlasov_grid* grid);
+
+/*
+ * Adjoint of vlasov_step (FP32): the forward stages are recomputed from f_in
+ * into `work`, then the nine sweeps are transposed in reverse order.
+ * lam_in = (d f_out / d f_in)^T lam_out; lam_g_n and lam_g_np1 (FP32
+ * [3][cells]) are ADDED the gradients with respect to the fields at t^n and
+ * t^{n+1}.  Outflow tallies carry no adjoint.
+ */
+int vlasov_step_adj(const vlasov_grid* grid, vlasov_vbc vbc, const float* f_in,
+                    const float* g_n, const float* g_np1, double dt, double a2inv,
+                    const float* lam_out, float* lam_in, float* lam_g_n, float* lam_g_np1,
+                    void* work, size_t work_bytes, void* stream);
+
+/*
+ * Adjoint of vlasov_moments (section 5.1.3) at the forward result rho,
+ * umean (FP64 device arrays from vlasov_moments):
+ *   lam_f[c][u] += du^3 lam_rho[c] + du^3 sum_a lam_umean[a][c] (u_a - umean[a][c]) / rho[c]
+ * (the umean term only where rho[c] != 0; lam_umean, rho and umean may be
+ * NULL together).  lam_f is FP32 in the layout of f and is accumulated.
+ */
+int vlasov_moments_adj(const vlasov_grid* grid, const double* rho, const double* umean,
+                       const double* lam_rho, const double* lam_umean, float* lam_f,
+                       void* stream);
+
 /* Deterministic FP64 sum of x[0..n) into *out (device pointers): a single
  * work-group, fixed order.  Used for total mass and total outflow. */
 int vlasov_sum_f64(const double* x, int64_t n, double* out, void* stream);

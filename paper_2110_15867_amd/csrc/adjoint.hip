@@ -1,0 +1,399 @@
+// Tangent-linear and adjoint sweeps (FP32 storage only).
+//
+// With the limiter's selections frozen at the forward input, one sweep of a
+// line is a linear map of the cell values, f' = J f, and a smooth function of
+// the fractional shift nu (through the semi-Lagrangian weights and the
+// factor mu of the flux).  Each interface flux is linearised as
+//   Phi = sum_k W_k f_{j+k} (upwind frame, k = -2..2),  dPhi/dmu,
+// by re-running the forward arithmetic of flux_mag on the forward input with
+// the same FP32 operations, so every selection (early-out, curvature
+// minmods, bounds, median, positivity clamp) is the forward's own, and then
+// reading off which candidate each selection returned.  Ties between equal
+// candidates are resolved as in the FP64 oracle: min and max keep their first
+// argument, the median is max(min(x,y), min(max(x,y),z)).
+//
+//  tangent: out_dot_i = v_{i-N} - (Phi_dot_{j+1/2} - Phi_dot_{j-1/2}), j = i-N,
+//           Phi_dot = W . v + dPhi/dmu * mu_dot
+//  adjoint: lam_in_r = lam_{r+N} + sum_{k} psi_{r-k} W_{r-k}[k],
+//           psi_j = lam_{j+N+1} - lam_{j+N}, lam_mu = sum_j psi_j dPhi_j/dmu
+// (all in the walk frame of the line; lines with a negative shift are walked
+// mirrored, where mu = -nu).  The adjoint gathers: each input cell is written
+// once, from a sliding window of the five interfaces that read it.
+//
+// One thread per line with direct strided loads: these kernels run once per
+// gradient evaluation and favour simplicity over bandwidth.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "launch.hpp"
+#include "rows.hpp"
+#include "sl_mpp5.hpp"
+
+namespace vlasov {
+
+namespace {
+
+// Derivatives of the interface-value weights with respect to mu.
+struct WeightSlopes {
+    float d0, d1, d2, d3, d4;
+};
+
+__device__ __forceinline__ WeightSlopes sl5_weight_slopes(float mu)
+{
+    const float m2 = mu * mu, m3 = m2 * mu;
+    const float k = 1.0f / 120.0f;
+    WeightSlopes s;
+    s.d0 = (4.0f * m3 - 10.0f * mu) * k;
+    s.d1 = -(16.0f * m3 - 15.0f * m2 - 60.0f * mu + 5.0f) * k;
+    s.d2 = (24.0f * m3 - 45.0f * m2 - 80.0f * mu + 75.0f) * k;
+    s.d3 = -(16.0f * m3 - 45.0f * m2 - 20.0f * mu + 75.0f) * k;
+    s.d4 = (4.0f * m3 - 15.0f * m2 + 10.0f * mu + 5.0f) * k;
+    return s;
+}
+
+// Linear form over the stencil (a, b, c, d, e).
+struct Lin {
+    float w[5];
+};
+
+__device__ __forceinline__ Lin lin_unit(int k)
+{
+    Lin r;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r.w[q] = q == k ? 1.0f : 0.0f;
+    return r;
+}
+
+__device__ __forceinline__ Lin lin_comb(float p, const Lin& x, float q, const Lin& y)
+{
+    Lin r;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) r.w[i] = p * x.w[i] + q * y.w[i];
+    return r;
+}
+
+// Selections with the oracle's tie rules, on (value, form) pairs.
+struct VL {
+    float v;
+    Lin l;
+};
+__device__ __forceinline__ VL vmin2(const VL& x, const VL& y) { return x.v <= y.v ? x : y; }
+__device__ __forceinline__ VL vmax2(const VL& x, const VL& y) { return x.v >= y.v ? x : y; }
+__device__ __forceinline__ VL vmed3(const VL& x, const VL& y, const VL& z)
+{
+    return vmax2(vmin2(x, y), vmin2(vmax2(x, y), z));
+}
+__device__ __forceinline__ VL vminmod4(const VL& w, const VL& x, const VL& y, const VL& z)
+{
+    if (w.v > 0.0f && x.v > 0.0f && y.v > 0.0f && z.v > 0.0f)
+        return vmin2(vmin2(w, x), vmin2(y, z));
+    if (w.v < 0.0f && x.v < 0.0f && y.v < 0.0f && z.v < 0.0f)
+        return vmax2(vmax2(w, x), vmax2(y, z));
+    VL r;
+    r.v = 0.0f;
+    r.l = lin_comb(0.0f, lin_unit(0), 0.0f, lin_unit(0));
+    return r;
+}
+
+struct FluxLin {
+    float phi;      // flux magnitude (identical to flux_mag)
+    float W[5];     // d phi / d (a..e)
+    float dmu;      // d phi / d mu
+};
+
+// The forward flux with its frozen linearisation.  The values follow
+// flux_mag / mp_bounded operation by operation.
+__device__ FluxLin flux_lin(const Stencil& s, const LineShift& sh, const WeightSlopes& ds)
+{
+    float fhat = sh.w0 * s.a;
+    fhat = fmaf(sh.w1, s.b, fhat);
+    fhat = fmaf(sh.w2, s.c, fhat);
+    fhat = fmaf(sh.w3, s.d, fhat);
+    fhat = fmaf(sh.w4, s.e, fhat);
+    const float m = med3(s.d0, 4.0f * s.dm1, 0.0f);
+    const float y = fhat - s.c;
+    VL L;
+    L.v = fhat;
+    L.l.w[0] = sh.w0; L.l.w[1] = sh.w1; L.l.w[2] = sh.w2; L.l.w[3] = sh.w3; L.l.w[4] = sh.w4;
+    bool L_is_fhat = true;
+    if (med3(y, 0.0f, m) != y) {
+        // curvatures as differences of differences (as in mp_bounded)
+        const float Dmv = s.dm1 - s.dm2, D0v = s.d0 - s.dm1, Dpv = s.dp1 - s.d0;
+        VL Dm{Dmv, {{1.0f, -2.0f, 1.0f, 0.0f, 0.0f}}};
+        VL D0{D0v, {{0.0f, 1.0f, -2.0f, 1.0f, 0.0f}}};
+        VL Dp{Dpv, {{0.0f, 0.0f, 1.0f, -2.0f, 1.0f}}};
+        // curv_minmod(Da, Db) = minmod(4Da-Db, 4Db-Da, Da, Db)
+        VL p1{fmaf(4.0f, D0v, -Dpv), lin_comb(4.0f, D0.l, -1.0f, Dp.l)};
+        VL q1{fmaf(4.0f, Dpv, -D0v), lin_comb(4.0f, Dp.l, -1.0f, D0.l)};
+        const VL Mp = vminmod4(p1, q1, D0, Dp);
+        VL p2{fmaf(4.0f, Dmv, -D0v), lin_comb(4.0f, Dm.l, -1.0f, D0.l)};
+        VL q2{fmaf(4.0f, D0v, -Dmv), lin_comb(4.0f, D0.l, -1.0f, Dm.l)};
+        const VL Mm = vminmod4(p2, q2, Dm, D0);
+        const VL c{s.c, lin_unit(2)};
+        const VL d{s.d, lin_unit(3)};
+        const Lin cb = lin_comb(1.0f, lin_unit(2), -1.0f, lin_unit(1));
+        VL fUL{fmaf(4.0f, s.dm1, s.c), lin_comb(4.0f, cb, 1.0f, c.l)};
+        VL fMD{0.5f * ((s.c + s.d) - Mp.v),
+               lin_comb(0.5f, lin_comb(1.0f, c.l, 1.0f, d.l), -0.5f, Mp.l)};
+        VL fLC{fmaf(4.0f / 3.0f, Mm.v, fmaf(0.5f, s.dm1, s.c)),
+               lin_comb(4.0f / 3.0f, Mm.l, 1.0f, lin_comb(0.5f, cb, 1.0f, c.l))};
+        const VL lo = vmax2(vmin2(vmin2(c, d), fMD), vmin2(vmin2(c, fUL), fLC));
+        const VL hi = vmin2(vmax2(vmax2(c, d), fMD), vmax2(vmax2(c, fUL), fLC));
+        const VL r = vmed3(L, lo, hi);
+        L_is_fhat = r.v == L.v && r.l.w[0] == L.l.w[0] && r.l.w[1] == L.l.w[1] &&
+                    r.l.w[2] == L.l.w[2] && r.l.w[3] == L.l.w[3] && r.l.w[4] == L.l.w[4];
+        L = r;
+    }
+    float Ldmu = 0.0f;
+    if (L_is_fhat) {
+        Ldmu = ds.d0 * s.a;
+        Ldmu = fmaf(ds.d1, s.b, Ldmu);
+        Ldmu = fmaf(ds.d2, s.c, Ldmu);
+        Ldmu = fmaf(ds.d3, s.d, Ldmu);
+        Ldmu = fmaf(ds.d4, s.e, Ldmu);
+    }
+    // positivity clamp med3(mu L, 0, c), oracle tie rules
+    const float x = sh.mu * L.v;
+    VL X{x, lin_comb(sh.mu, L.l, 0.0f, L.l)};
+    VL Z{0.0f, lin_comb(0.0f, L.l, 0.0f, L.l)};
+    VL C{s.c, lin_unit(2)};
+    const VL r = vmed3(X, Z, C);
+    FluxLin out;
+    out.phi = r.v;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out.W[q] = r.l.w[q];
+    const bool took_x = r.v == X.v && r.l.w[0] == X.l.w[0] && r.l.w[1] == X.l.w[1] &&
+                        r.l.w[2] == X.l.w[2] && r.l.w[3] == X.l.w[3] && r.l.w[4] == X.l.w[4];
+    out.dmu = took_x ? fmaf(sh.mu, Ldmu, L.v) : 0.0f;
+    return out;
+}
+
+// Stencil of interface j+1/2 in the walk frame from a 5-value window.
+__device__ __forceinline__ Stencil make_stencil(const float* w)
+{
+    return Stencil{w[0], w[1], w[2], w[3], w[4], w[1] - w[0], w[2] - w[1], w[3] - w[2],
+                   w[4] - w[3]};
+}
+
+using Reader32 = GlobalReader<PREC_F32, 1, false>;
+
+// Tangent of one line: x = forward input, v = input tangent, mu_dot = d mu.
+__device__ void line_tangent(Reader32& rx, Reader32& rv, float* out, long stride, int M, int dir,
+                             const LineShift& sh, bool periodic, float mu_dot)
+{
+    const WeightSlopes ds = sl5_weight_slopes(sh.mu);
+    const int N = sh.N;
+    float wx[5], wv[5];
+    rx.seek(-N - 3);
+    rv.seek(-N - 3);
+    for (int q = 0; q < 5; ++q) {
+        rx.next(&wx[q]);
+        rv.next(&wv[q]);
+    }
+    auto dphi = [&](const float* xs, const float* vs) {
+        const FluxLin fl = flux_lin(make_stencil(xs), sh, ds);
+        float t = fl.dmu * mu_dot;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) t = fmaf(fl.W[q], vs[q], t);
+        return t;
+    };
+    float old = dphi(wx, wv);                     // interface j0 - 1/2
+    for (int i = 0; i < M; ++i) {
+        for (int q = 0; q < 4; ++q) {
+            wx[q] = wx[q + 1];
+            wv[q] = wv[q + 1];
+        }
+        rx.next(&wx[4]);
+        rv.next(&wv[4]);
+        const float nw = dphi(wx, wv);            // interface j + 1/2, j = i - N
+        const int p = dir > 0 ? i : M - 1 - i;
+        out[(long)p * stride] = wv[2] - (nw - old);
+        old = nw;
+    }
+}
+
+// Adjoint of one line: x = forward input, lam = output adjoint (frame rows
+// read through rl, which starts N rows later).  Writes lam_in and returns
+// lam_mu.
+__device__ float line_adjoint(Reader32& rx, Reader32& rl, float* lam_in, long stride, int M,
+                              int dir, const LineShift& sh, bool periodic)
+{
+    const WeightSlopes ds = sl5_weight_slopes(sh.mu);
+    const int N = sh.N;
+    // interfaces j = -2 .. M+1 ; interface j reads x_{j-2..j+2}, psi_j needs
+    // lam_{j+N}, lam_{j+N+1}
+    float wx[5];
+    rx.seek(-4);
+    for (int q = 0; q < 5; ++q) rx.next(&wx[q]);    // x_{-4..0}: stencil of j = -2
+    rl.seek(N - 2);
+    float lam_lo, lam_hi;
+    rl.next(&lam_lo);                                // lam_{-2+N}
+    // window of the last five interfaces: psi and weights
+    float psi[5], W[5][5];
+    float lam_mu = 0.0f;
+    // identity term source: lam_{r+N} for r = j-2 -> read separately
+    Reader32 rid = rl;
+    rid.seek(N);                                     // lam_{0+N}
+    for (int j = -2; j <= M + 1; ++j) {
+        if (j > -2) {
+            for (int q = 0; q < 4; ++q) wx[q] = wx[q + 1];
+            rx.next(&wx[4]);                         // x_{j+2}
+        }
+        rl.next(&lam_hi);                            // lam_{j+N+1}
+        const FluxLin fl = flux_lin(make_stencil(wx), sh, ds);
+        const float ps = lam_hi - lam_lo;
+        lam_lo = lam_hi;
+        if (periodic ? (j >= 0 && j < M) : true) lam_mu = fmaf(ps, fl.dmu, lam_mu);
+        // slide the interface window: slot 4 holds interface j
+        for (int q = 0; q < 4; ++q) {
+            psi[q] = psi[q + 1];
+            for (int k = 0; k < 5; ++k) W[q][k] = W[q + 1][k];
+        }
+        psi[4] = ps;
+        for (int k = 0; k < 5; ++k) W[4][k] = fl.W[k];
+        if (j >= 2) {
+            // row r = j-2 is read by interfaces r-2..r+2 = slots 0..4 at offsets k = 2..-2
+            const int r = j - 2;
+            float id;
+            rid.next(&id);                           // lam_{r+N}
+            float acc = id;
+            for (int q = 0; q < 5; ++q) acc = fmaf(psi[q], W[q][4 - q], acc);
+            const int p = dir > 0 ? r : M - 1 - r;
+            lam_in[(long)p * stride] = acc;
+        }
+    }
+    return lam_mu;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_position_tan(const float* __restrict__ f,
+                                                      const float* __restrict__ v,
+                                                      float* __restrict__ out, PosArgs a)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.O * a.I) return;
+    const long o = t / a.I, k = t - (t / a.I) * a.I;
+    const int jl = (int)(((k % a.Nu) / a.pst) % a.nshift);
+    const LineShift sh = split_shift(a.shift[jl], a.M, true);
+    const int dir = sh.neg ? -1 : 1;
+    const long base = o * (long)a.M * a.I + k;
+    Reader32 rx{f + base, nullptr, a.I, 0, a.M, dir, true, 0};
+    Reader32 rv{v + base, nullptr, a.I, 0, a.M, dir, true, 0};
+    line_tangent(rx, rv, out + base, a.I, a.M, dir, sh, true, 0.0f);
+}
+
+__global__ void __launch_bounds__(256) k_position_adj(const float* __restrict__ f,
+                                                      const float* __restrict__ lam,
+                                                      float* __restrict__ lam_in, PosArgs a)
+{
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.O * a.I) return;
+    const long o = t / a.I, k = t - (t / a.I) * a.I;
+    const int jl = (int)(((k % a.Nu) / a.pst) % a.nshift);
+    const LineShift sh = split_shift(a.shift[jl], a.M, true);
+    const int dir = sh.neg ? -1 : 1;
+    const long base = o * (long)a.M * a.I + k;
+    Reader32 rx{f + base, nullptr, a.I, 0, a.M, dir, true, 0};
+    Reader32 rl{lam + base, nullptr, a.I, 0, a.M, dir, true, 0};
+    line_adjoint(rx, rl, lam_in + base, a.I, a.M, dir, sh, true);
+}
+
+// Velocity sweeps: one work-group per spatial cell; lines of the cell are
+// (sub, k) with line start ((cell*nsub + sub) * M) * I + k.
+__global__ void __launch_bounds__(256) k_velocity_tan(const float* __restrict__ f,
+                                                      const float* __restrict__ v,
+                                                      float* __restrict__ out,
+                                                      const float* __restrict__ g_dot, VelArgs a)
+{
+    const long cell = blockIdx.x;
+    const double s = (double)a.g[cell] * a.factor;
+    const LineShift sh = split_shift(s, a.M, a.periodic);
+    const int dir = sh.neg ? -1 : 1;
+    // d mu / d s = +1 (rightward) or -1 (walked mirrored); s_dot = g_dot dt / du
+    const float s_dot = g_dot != nullptr ? (float)((double)g_dot[cell] * a.factor) : 0.0f;
+    const float mu_dot = sh.neg ? -s_dot : s_dot;
+    const long lpc = a.nsub * a.I;
+    for (long l = threadIdx.x; l < lpc; l += blockDim.x) {
+        const long sub = l / a.I, k = l - (l / a.I) * a.I;
+        const long base = ((cell * a.nsub + sub) * a.M) * a.I + k;
+        Reader32 rx{f + base, nullptr, a.I, 0, a.M, dir, a.periodic, 0};
+        Reader32 rv{v + base, nullptr, a.I, 0, a.M, dir, a.periodic, 0};
+        line_tangent(rx, rv, out + base, a.I, a.M, dir, sh, a.periodic, mu_dot);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_velocity_adj(const float* __restrict__ f,
+                                                      const float* __restrict__ lam,
+                                                      float* __restrict__ lam_in,
+                                                      float* __restrict__ lam_g, VelArgs a)
+{
+    __shared__ double red[4];
+    const long cell = blockIdx.x;
+    const double s = (double)a.g[cell] * a.factor;
+    const LineShift sh = split_shift(s, a.M, a.periodic);
+    const int dir = sh.neg ? -1 : 1;
+    const long lpc = a.nsub * a.I;
+    double mine = 0.0;
+    for (long l = threadIdx.x; l < lpc; l += blockDim.x) {
+        const long sub = l / a.I, k = l - (l / a.I) * a.I;
+        const long base = ((cell * a.nsub + sub) * a.M) * a.I + k;
+        Reader32 rx{f + base, nullptr, a.I, 0, a.M, dir, a.periodic, 0};
+        Reader32 rl{lam + base, nullptr, a.I, 0, a.M, dir, a.periodic, 0};
+        mine += (double)line_adjoint(rx, rl, lam_in + base, a.I, a.M, dir, sh, a.periodic);
+    }
+    if (lam_g != nullptr) {
+        const double tot = block_sum(mine, red);
+        // lam_s = +lam_mu (rightward) or -lam_mu (mirrored); ds/dg = dt/du
+        if (threadIdx.x == 0) lam_g[cell] += (float)((sh.neg ? -tot : tot) * a.factor);
+    }
+}
+
+hipError_t launch_position_tan(const float* f, const float* v, float* out, const PosArgs& a,
+                               hipStream_t st)
+{
+    const long total = a.O * a.I;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_position_tan, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, f,
+                       v, out, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_position_adj(const float* f, const float* lam, float* lam_in, const PosArgs& a,
+                               hipStream_t st)
+{
+    const long total = a.O * a.I;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_position_adj, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, f,
+                       lam, lam_in, a);
+    return hipGetLastError();
+}
+
+static unsigned vel_block(const VelArgs& a)
+{
+    long bs = ((a.nsub * a.I + 63) / 64) * 64;
+    return (unsigned)(bs > 256 ? 256 : bs);
+}
+
+hipError_t launch_velocity_tan(const float* f, const float* v, float* out, const float* g_dot,
+                               const VelArgs& a, hipStream_t st)
+{
+    if (a.cells == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_velocity_tan, dim3((unsigned)a.cells), dim3(vel_block(a)), 0, st, f, v,
+                       out, g_dot, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_velocity_adj(const float* f, const float* lam, float* lam_in, float* lam_g,
+                               const VelArgs& a, hipStream_t st)
+{
+    if (a.cells == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_velocity_adj, dim3((unsigned)a.cells), dim3(vel_block(a)), 0, st, f,
+                       lam, lam_in, lam_g, a);
+    return hipGetLastError();
+}
+
+}  // namespace vlasov

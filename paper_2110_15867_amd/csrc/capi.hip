@@ -96,12 +96,10 @@ double position_shift(const vlasov_grid* g, int a, long j, double dt_over_a2)
     return u * factor;
 }
 
-int run_position(const vlasov_grid* g, const Dims& d, int axis, int prec, const void* fin,
-                 const float* sin, void* fout, float* sout, double dt_over_a2, hipStream_t st)
+int make_pos_args(const vlasov_grid* g, const Dims& d, int axis, double dt_over_a2, PosArgs& a)
 {
     if (!isfinite(dt_over_a2)) return VLASOV_ERR_NONFINITE;
     if (d.nu[axis] > kMaxShiftTable) return VLASOV_ERR_SHAPE;
-    PosArgs a;
     memset(&a, 0, sizeof(a));
     a.O = 1;
     for (int b = 0; b < axis; ++b) a.O *= d.n[b];
@@ -118,18 +116,25 @@ int run_position(const vlasov_grid* g, const Dims& d, int axis, int prec, const 
         a.shift[j] = position_shift(g, axis, j, dt_over_a2);
         if (!isfinite(a.shift[j])) return VLASOV_ERR_NONFINITE;
     }
+    return VLASOV_OK;
+}
+
+int run_position(const vlasov_grid* g, const Dims& d, int axis, int prec, const void* fin,
+                 const float* sin, void* fout, float* sout, double dt_over_a2, hipStream_t st)
+{
+    PosArgs a;
+    const int rc = make_pos_args(g, d, axis, dt_over_a2, a);
+    if (rc) return rc;
     return from_hip(launch_position(prec, fin, sin, fout, sout, a, st));
 }
 
-int run_velocity(const vlasov_grid* g, const Dims& d, int axis, int prec, int vbc,
-                 const void* fin, const float* sin, void* fout, float* sout, const float* field,
-                 double dt, double* outflow, hipStream_t st)
+int make_vel_args(const vlasov_grid* g, const Dims& d, int axis, int vbc, const float* field,
+                  double dt, double* outflow, VelArgs& a)
 {
     if (!isfinite(dt)) return VLASOV_ERR_NONFINITE;
     const double du = 2.0 * g->umax[axis] / g->nu[axis];
     const double factor = dt / du;
     if (!isfinite(factor)) return VLASOV_ERR_NONFINITE;
-    VelArgs a;
     memset(&a, 0, sizeof(a));
     a.g = field + (long)axis * d.cells;
     a.factor = factor;
@@ -145,12 +150,23 @@ int run_velocity(const vlasov_grid* g, const Dims& d, int axis, int prec, int vb
         a.nsub = d.nu[0] * d.nu[1];
         a.V = 1;
         a.G = 1;
-        return from_hip(launch_vel_uz(prec, fin, sin, fout, sout, a, st));
+    } else {
+        a.I = axis == 0 ? d.nu[1] * d.nu[2] : d.nu[2];
+        a.nsub = axis == 0 ? 1 : d.nu[0];
+        a.V = vector_width(d.nu[2]);
+        a.G = (int)(d.nu[2] / a.V);
     }
-    a.I = axis == 0 ? d.nu[1] * d.nu[2] : d.nu[2];
-    a.nsub = axis == 0 ? 1 : d.nu[0];
-    a.V = vector_width(d.nu[2]);
-    a.G = (int)(d.nu[2] / a.V);
+    return VLASOV_OK;
+}
+
+int run_velocity(const vlasov_grid* g, const Dims& d, int axis, int prec, int vbc,
+                 const void* fin, const float* sin, void* fout, float* sout, const float* field,
+                 double dt, double* outflow, hipStream_t st)
+{
+    VelArgs a;
+    const int rc = make_vel_args(g, d, axis, vbc, field, dt, outflow, a);
+    if (rc) return rc;
+    if (axis == 2) return from_hip(launch_vel_uz(prec, fin, sin, fout, sout, a, st));
     return from_hip(launch_vel_strided(prec, fin, sin, fout, sout, a, st));
 }
 
@@ -422,6 +438,200 @@ int vlasov_moments(const vlasov_grid* g, vlasov_prec prec, const void* f, const 
     if (rc || mass == nullptr) return rc;
     const double dx3 = (g->L[0] / g->n[0]) * (g->L[1] / g->n[1]) * (g->L[2] / g->n[2]);
     return from_hip(launch_sum(rho, d.cells, dx3, mass, st));
+}
+
+// ---------------------------------------------------------------------------
+// Tangents and adjoints (FP32 storage)
+// ---------------------------------------------------------------------------
+static int check_adj_io(const vlasov_grid* g, Dims& d, const void* a, const void* b, const void* out)
+{
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (a == nullptr || b == nullptr || out == nullptr) return VLASOV_ERR_NULL;
+    const size_t fb = (size_t)d.total * sizeof(float);
+    if (overlap(out, fb, a, fb) || overlap(out, fb, b, fb)) return VLASOV_ERR_ALIAS;
+    return VLASOV_OK;
+}
+
+static int position_tan(const vlasov_grid* g, int axis, const float* f, const float* v,
+                        float* out, double dta, void* stream)
+{
+    Dims d;
+    int rc = check_adj_io(g, d, f, v, out);
+    if (rc) return rc;
+    PosArgs a;
+    if ((rc = make_pos_args(g, d, axis, dta, a))) return rc;
+    return from_hip(launch_position_tan(f, v, out, a, (hipStream_t)stream));
+}
+
+static int position_adj(const vlasov_grid* g, int axis, const float* f, const float* lam,
+                        float* lam_in, double dta, void* stream)
+{
+    Dims d;
+    int rc = check_adj_io(g, d, f, lam, lam_in);
+    if (rc) return rc;
+    PosArgs a;
+    if ((rc = make_pos_args(g, d, axis, dta, a))) return rc;
+    return from_hip(launch_position_adj(f, lam, lam_in, a, (hipStream_t)stream));
+}
+
+static int velocity_tan(const vlasov_grid* g, int axis, int vbc, const float* f,
+                        const float* field, const float* g_dot, double dt, const float* v,
+                        float* out, void* stream)
+{
+    Dims d;
+    int rc = check_adj_io(g, d, f, v, out);
+    if (rc) return rc;
+    if (vbc != VLASOV_VBC_OUTFLOW && vbc != VLASOV_VBC_PERIODIC) return VLASOV_ERR_PREC;
+    if (field == nullptr) return VLASOV_ERR_NULL;
+    VelArgs a;
+    if ((rc = make_vel_args(g, d, axis, vbc, field, dt, nullptr, a))) return rc;
+    const float* gd = g_dot != nullptr ? g_dot + (long)axis * d.cells : nullptr;
+    return from_hip(launch_velocity_tan(f, v, out, gd, a, (hipStream_t)stream));
+}
+
+static int velocity_adj(const vlasov_grid* g, int axis, int vbc, const float* f,
+                        const float* field, double dt, const float* lam, float* lam_in,
+                        float* lam_g, void* stream)
+{
+    Dims d;
+    int rc = check_adj_io(g, d, f, lam, lam_in);
+    if (rc) return rc;
+    if (vbc != VLASOV_VBC_OUTFLOW && vbc != VLASOV_VBC_PERIODIC) return VLASOV_ERR_PREC;
+    if (field == nullptr) return VLASOV_ERR_NULL;
+    if (lam_g != nullptr && overlap(lam_in, (size_t)d.total * 4, lam_g, 3 * d.cells * 4))
+        return VLASOV_ERR_ALIAS;
+    VelArgs a;
+    if ((rc = make_vel_args(g, d, axis, vbc, field, dt, nullptr, a))) return rc;
+    float* lg = lam_g != nullptr ? lam_g + (long)axis * d.cells : nullptr;
+    return from_hip(launch_velocity_adj(f, lam, lam_in, lg, a, (hipStream_t)stream));
+}
+
+#define VL_POS_DERIV(ax, idx)                                                                  \
+    int vlasov_advect_##ax##_tan(const vlasov_grid* g, const float* f_in, const float* v_in,    \
+                                 float* v_out, double dt_over_a2, void* stream)                 \
+    {                                                                                          \
+        return position_tan(g, idx, f_in, v_in, v_out, dt_over_a2, stream);                     \
+    }                                                                                          \
+    int vlasov_advect_##ax##_adj(const vlasov_grid* g, const float* f_in, const float* lam_out, \
+                                 float* lam_in, double dt_over_a2, void* stream)                \
+    {                                                                                          \
+        return position_adj(g, idx, f_in, lam_out, lam_in, dt_over_a2, stream);                 \
+    }
+VL_POS_DERIV(x, 0)
+VL_POS_DERIV(y, 1)
+VL_POS_DERIV(z, 2)
+#undef VL_POS_DERIV
+
+#define VL_VEL_DERIV(ax, idx)                                                                   \
+    int vlasov_advect_u##ax##_tan(const vlasov_grid* g, vlasov_vbc vbc, const float* f_in,       \
+                                  const float* field, const float* g_dot, double dt,             \
+                                  const float* v_in, float* v_out, void* stream)                 \
+    {                                                                                           \
+        return velocity_tan(g, idx, vbc, f_in, field, g_dot, dt, v_in, v_out, stream);           \
+    }                                                                                           \
+    int vlasov_advect_u##ax##_adj(const vlasov_grid* g, vlasov_vbc vbc, const float* f_in,       \
+                                  const float* field, double dt, const float* lam_out,           \
+                                  float* lam_in, float* lam_g, void* stream)                     \
+    {                                                                                           \
+        return velocity_adj(g, idx, vbc, f_in, field, dt, lam_out, lam_in, lam_g, stream);       \
+    }
+VL_VEL_DERIV(x, 0)
+VL_VEL_DERIV(y, 1)
+VL_VEL_DERIV(z, 2)
+#undef VL_VEL_DERIV
+
+size_t vlasov_step_adj_workspace_bytes(const vlasov_grid* grid)
+{
+    Dims d;
+    if (!dims_of(grid, d)) return 0;
+    return 9 * align_up((size_t)d.total * sizeof(float));
+}
+
+int vlasov_step_adj(const vlasov_grid* g, vlasov_vbc vbc, const float* fin, const float* g_n,
+                    const float* g_np1, double dt, double a2inv, const float* lam_out,
+                    float* lam_in, float* lam_g_n, float* lam_g_np1, void* work,
+                    size_t work_bytes, void* stream)
+{
+    Dims d;
+    int rc = check_adj_io(g, d, fin, lam_out, lam_in);
+    if (rc) return rc;
+    if (vbc != VLASOV_VBC_OUTFLOW && vbc != VLASOV_VBC_PERIODIC) return VLASOV_ERR_PREC;
+    if (g_n == nullptr || g_np1 == nullptr) return VLASOV_ERR_NULL;
+    if (!isfinite(dt) || !isfinite(a2inv) || !isfinite(dt * a2inv)) return VLASOV_ERR_NONFINITE;
+    const size_t need = vlasov_step_adj_workspace_bytes(g);
+    if (work == nullptr || work_bytes < need) return VLASOV_ERR_WORKSPACE;
+    const size_t fb = (size_t)d.total * sizeof(float);
+    if (overlap(work, need, fin, fb) || overlap(work, need, lam_out, fb) ||
+        overlap(work, need, lam_in, fb))
+        return VLASOV_ERR_ALIAS;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t slot = align_up(fb);
+    float* stage[9];
+    stage[0] = const_cast<float*>(fin);
+    for (int k = 1; k < 9; ++k) stage[k] = (float*)((char*)work + (k - 1) * slot);
+    float* lw = (float*)((char*)work + 8 * slot);
+    const double h = 0.5 * dt, dta = dt * a2inv;
+    // forward stages: stage[k] is the input of sweep k of Eq. (5)
+    if ((rc = run_velocity(g, d, 0, VLASOV_F32, vbc, stage[0], nullptr, stage[1], nullptr, g_n, h, nullptr, st))) return rc;
+    if ((rc = run_velocity(g, d, 1, VLASOV_F32, vbc, stage[1], nullptr, stage[2], nullptr, g_n, h, nullptr, st))) return rc;
+    if ((rc = run_velocity(g, d, 2, VLASOV_F32, vbc, stage[2], nullptr, stage[3], nullptr, g_n, h, nullptr, st))) return rc;
+    if ((rc = run_position(g, d, 2, VLASOV_F32, stage[3], nullptr, stage[4], nullptr, dta, st))) return rc;
+    if ((rc = run_position(g, d, 1, VLASOV_F32, stage[4], nullptr, stage[5], nullptr, dta, st))) return rc;
+    if ((rc = run_position(g, d, 0, VLASOV_F32, stage[5], nullptr, stage[6], nullptr, dta, st))) return rc;
+    if ((rc = run_velocity(g, d, 0, VLASOV_F32, vbc, stage[6], nullptr, stage[7], nullptr, g_np1, h, nullptr, st))) return rc;
+    if ((rc = run_velocity(g, d, 1, VLASOV_F32, vbc, stage[7], nullptr, stage[8], nullptr, g_np1, h, nullptr, st))) return rc;
+    // reverse: lam_out -> lam_in -> lw -> lam_in -> ... -> lam_in (nine transposed sweeps)
+    const float* src = lam_out;
+    float* bufs[2] = {lam_in, lw};
+    int b = 0;
+    auto vadj = [&](int axis, int k, const float* field, float* lg) {
+        const int r = velocity_adj(g, axis, vbc, stage[k], field, h, src, bufs[b], lg, stream);
+        src = bufs[b];
+        b ^= 1;
+        return r;
+    };
+    auto padj = [&](int axis, int k) {
+        const int r = position_adj(g, axis, stage[k], src, bufs[b], dta, stream);
+        src = bufs[b];
+        b ^= 1;
+        return r;
+    };
+    if ((rc = vadj(2, 8, g_np1, lam_g_np1))) return rc;
+    if ((rc = vadj(1, 7, g_np1, lam_g_np1))) return rc;
+    if ((rc = vadj(0, 6, g_np1, lam_g_np1))) return rc;
+    if ((rc = padj(0, 5))) return rc;
+    if ((rc = padj(1, 4))) return rc;
+    if ((rc = padj(2, 3))) return rc;
+    if ((rc = vadj(2, 2, g_n, lam_g_n))) return rc;
+    if ((rc = vadj(1, 1, g_n, lam_g_n))) return rc;
+    return vadj(0, 0, g_n, lam_g_n);
+}
+
+int vlasov_moments_adj(const vlasov_grid* g, const double* rho, const double* umean,
+                       const double* lam_rho, const double* lam_umean, float* lam_f,
+                       void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (lam_f == nullptr || lam_rho == nullptr) return VLASOV_ERR_NULL;
+    if (lam_umean != nullptr && (rho == nullptr || umean == nullptr)) return VLASOV_ERR_NULL;
+    MomArgs a;
+    memset(&a, 0, sizeof(a));
+    a.cells = d.cells;
+    a.Nu = d.Nu;
+    a.nuz = d.nu[2];
+    a.du3 = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        a.nu[k] = (int)d.nu[k];
+        a.umin[k] = -g->umax[k];
+        a.du[k] = 2.0 * g->umax[k] / g->nu[k];
+        a.du3 *= a.du[k];
+    }
+    a.rho = const_cast<double*>(rho);
+    a.umean = const_cast<double*>(umean);
+    return from_hip(launch_moments_adj(a, lam_rho, lam_umean, lam_f, (hipStream_t)stream));
 }
 
 int vlasov_sum_f64(const double* x, int64_t n, double* out, void* stream)

@@ -73,5 +73,17 @@ struct MomArgs {
 hipError_t launch_moments(int prec, const void* f, const float* scale, const MomArgs& a,
                           hipStream_t st);
 hipError_t launch_sum(const double* x, long n, double scale, double* out, hipStream_t st);
+hipError_t launch_moments_adj(const MomArgs& a, const double* lam_rho, const double* lam_umean,
+                              float* lam_f, hipStream_t st);
+
+// tangents and adjoints (FP32 storage)
+hipError_t launch_position_tan(const float* f, const float* v, float* out, const PosArgs& a,
+                               hipStream_t st);
+hipError_t launch_position_adj(const float* f, const float* lam, float* lam_in, const PosArgs& a,
+                               hipStream_t st);
+hipError_t launch_velocity_tan(const float* f, const float* v, float* out, const float* g_dot,
+                               const VelArgs& a, hipStream_t st);
+hipError_t launch_velocity_adj(const float* f, const float* lam, float* lam_in, float* lam_g,
+                               const VelArgs& a, hipStream_t st);
 
 }  // namespace vlasov

@@ -99,6 +99,45 @@ hipError_t launch_moments(int prec, const void* f, const float* scale, const Mom
     }
 }
 
+// Adjoint of the moments: lam_f[c][u] += du^3 (lam_rho[c] + sum_a
+// lam_umean[a][c] (u_a - umean_a[c]) / rho[c]), the umean term only where
+// rho[c] != 0.  One work-group per cell.
+__global__ void __launch_bounds__(256) k_moments_adj(MomArgs a, const double* __restrict__ lam_rho,
+                                                     const double* __restrict__ lam_umean,
+                                                     float* __restrict__ lam_f)
+{
+    const long cell = blockIdx.x;
+    const long nyz = (long)a.nu[1] * a.nu[2];
+    const double base = a.du3 * lam_rho[cell];
+    double lu[3] = {0.0, 0.0, 0.0}, um[3] = {0.0, 0.0, 0.0};
+    if (lam_umean != nullptr && a.rho[cell] != 0.0) {
+        for (int k = 0; k < 3; ++k) {
+            lu[k] = a.du3 * lam_umean[k * a.cells + cell] / a.rho[cell];
+            um[k] = a.umean[k * a.cells + cell];
+        }
+    }
+    float* out = lam_f + cell * a.Nu;
+    for (long e = threadIdx.x; e < a.Nu; e += blockDim.x) {
+        const long jx = e / nyz;
+        const long jy = (e - jx * nyz) / a.nu[2];
+        const long jz = e - jx * nyz - jy * a.nu[2];
+        const double u0 = a.umin[0] + ((double)jx + 0.5) * a.du[0];
+        const double u1 = a.umin[1] + ((double)jy + 0.5) * a.du[1];
+        const double u2 = a.umin[2] + ((double)jz + 0.5) * a.du[2];
+        const double t = base + lu[0] * (u0 - um[0]) + lu[1] * (u1 - um[1]) + lu[2] * (u2 - um[2]);
+        out[e] += (float)t;
+    }
+}
+
+hipError_t launch_moments_adj(const MomArgs& a, const double* lam_rho, const double* lam_umean,
+                              float* lam_f, hipStream_t st)
+{
+    if (a.cells == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_moments_adj, dim3((unsigned)a.cells), dim3(256), 0, st, a, lam_rho,
+                       lam_umean, lam_f);
+    return hipGetLastError();
+}
+
 // One work-group, fixed order: thread t sums x[t], x[t+1024], ..., then a
 // fixed tree over the threads.
 __global__ void __launch_bounds__(1024) k_sum(const double* __restrict__ x, long n, double scale,

@@ -90,12 +90,14 @@ def _load():
 def _bind_adjoint(L):
     P, D, I, S = ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_size_t
     G = ctypes.POINTER(vlasov_grid)
-    if not hasattr(L, "vlasov_step_adj"):
-        return
     for ax in "xyz":
-        fn = getattr(L, f"vlasov_advect_{ax}_adj")
+        for kind in ("tan", "adj"):
+            fn = getattr(L, f"vlasov_advect_{ax}_{kind}")
+            fn.restype = I
+            fn.argtypes = [G, P, P, P, D, P]
+        fn = getattr(L, f"vlasov_advect_u{ax}_tan")
         fn.restype = I
-        fn.argtypes = [G, P, P, P, D, P]
+        fn.argtypes = [G, I, P, P, P, D, P, P, P]
         fn = getattr(L, f"vlasov_advect_u{ax}_adj")
         fn.restype = I
         fn.argtypes = [G, I, P, P, D, P, P, P, P]
@@ -104,7 +106,7 @@ def _bind_adjoint(L):
     L.vlasov_step_adj.restype = I
     L.vlasov_step_adj.argtypes = [G, I, P, P, P, D, D, P, P, P, P, P, S, P]
     L.vlasov_moments_adj.restype = I
-    L.vlasov_moments_adj.argtypes = [G, P, P, P, P, P]
+    L.vlasov_moments_adj.argtypes = [G, P, P, P, P, P, P]
 
 
 _lib = _load()
@@ -216,6 +218,62 @@ def vlasov_sum_f64(x, n, out, stream=None):
 def vlasov_stream_copy(src, dst, nbytes, stream=None):
     _check(_lib.vlasov_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)),
            "vlasov_stream_copy")
+
+
+def _pos_deriv(axis, kind):
+    name = f"vlasov_advect_{axis}_{kind}"
+
+    def fn(grid, f_in, x_in, x_out, dt_over_a2, stream=None):
+        _check(getattr(_lib, name)(ctypes.byref(grid), _ptr(f_in), _ptr(x_in), _ptr(x_out),
+                                   float(dt_over_a2), _stream(stream)), name)
+    fn.__name__ = name
+    return fn
+
+
+def _vel_tan(axis):
+    name = f"vlasov_advect_u{axis}_tan"
+
+    def fn(grid, vbc, f_in, g, g_dot, dt, v_in, v_out, stream=None):
+        _check(getattr(_lib, name)(ctypes.byref(grid), vbc, _ptr(f_in), _ptr(g), _ptr(g_dot),
+                                   float(dt), _ptr(v_in), _ptr(v_out), _stream(stream)), name)
+    fn.__name__ = name
+    return fn
+
+
+def _vel_adj(axis):
+    name = f"vlasov_advect_u{axis}_adj"
+
+    def fn(grid, vbc, f_in, g, dt, lam_out, lam_in, lam_g=None, stream=None):
+        _check(getattr(_lib, name)(ctypes.byref(grid), vbc, _ptr(f_in), _ptr(g), float(dt),
+                                   _ptr(lam_out), _ptr(lam_in), _ptr(lam_g), _stream(stream)),
+               name)
+    fn.__name__ = name
+    return fn
+
+
+for _ax in "xyz":
+    globals()[f"vlasov_advect_{_ax}_tan"] = _pos_deriv(_ax, "tan")
+    globals()[f"vlasov_advect_{_ax}_adj"] = _pos_deriv(_ax, "adj")
+    globals()[f"vlasov_advect_u{_ax}_tan"] = _vel_tan(_ax)
+    globals()[f"vlasov_advect_u{_ax}_adj"] = _vel_adj(_ax)
+
+
+def vlasov_step_adj_workspace_bytes(grid) -> int:
+    return _lib.vlasov_step_adj_workspace_bytes(ctypes.byref(grid))
+
+
+def vlasov_step_adj(grid, vbc, f_in, g_n, g_np1, dt, a2inv, lam_out, lam_in, lam_g_n, lam_g_np1,
+                    work, work_bytes, stream=None):
+    _check(_lib.vlasov_step_adj(ctypes.byref(grid), vbc, _ptr(f_in), _ptr(g_n), _ptr(g_np1),
+                                float(dt), float(a2inv), _ptr(lam_out), _ptr(lam_in),
+                                _ptr(lam_g_n), _ptr(lam_g_np1), _ptr(work), int(work_bytes),
+                                _stream(stream)), "vlasov_step_adj")
+
+
+def vlasov_moments_adj(grid, rho, umean, lam_rho, lam_umean, lam_f, stream=None):
+    _check(_lib.vlasov_moments_adj(ctypes.byref(grid), _ptr(rho), _ptr(umean), _ptr(lam_rho),
+                                   _ptr(lam_umean), _ptr(lam_f), _stream(stream)),
+           "vlasov_moments_adj")
 
 
 # --- convenience (allocation with torch, then the entry points) ----------------------------
