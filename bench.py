@@ -38,6 +38,30 @@ def algorithmic_bytes_per_cell(prec: int, nuz: int) -> float:
     return 2.0 * (2.0 + 4.0 / nuz)
 
 
+def measured_traffic(prec: int, kernel: str, nu: int, nx: int):
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    import glob
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for fn in sorted(glob.glob(os.path.join(ROOT, "paper_2110_15867_amd", "csrc", "*"))):
+        h.update(os.path.basename(fn).encode())
+        with open(fn, "rb") as fh:
+            h.update(fh.read())
+    data = json.load(open(path)).get({0: "f32", 1: "f16", 2: "bf16"}[prec])
+    if not data or data.get("source_sha256") != h.hexdigest():
+        return None
+    if kernel == "kick":
+        name = f"k_kick<{prec}, {nu}, {nu}, {nu}>"
+    else:
+        name = f"k_position<{prec}, {1 if kernel == 'z' else 4}, {nx}>"
+    return data["bytes_per_dispatch"].get(name)
+
+
 def cpu_baseline(seconds: float = 12.0):
     """FP64 oracle Strang step on the 16^3 x 16^3 workload (same recipe), host cores."""
     import numpy as np
@@ -225,7 +249,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(prec, dominant, w.nu[0], w.n[0]),
             "frac_of_copy_probe": achieved / copy_gbs,
         },
     }
