@@ -36,7 +36,7 @@ __device__ __forceinline__ void storage_round_line(float* line)
         x[i] = line[i];
         m = fmaxf(m, fabsf(x[i]));
     }
-    const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+    const float inv = inv_scale(m);
 #pragma unroll
     for (int i = 0; i < NZ; ++i) line[i] = Codec<P>::dec(quantize<P>(x[i], inv)) * m;
 }
@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(NY * NZ) k_kick(const typename Codec<P>::T* __
                 float m = 0.0f;
 #pragma unroll
                 for (int i = 0; i < NZ; ++i) m = fmaxf(m, fabsf(wr.out[i]));
-                inv = m > 0.0f ? 1.0f / m : 0.0f;
+                inv = inv_scale(m);
                 sout[cell * NL + t] = m;
             }
 #pragma unroll

@@ -32,13 +32,16 @@ struct GlobalReader {
 
     __device__ void seek(int r)
     {
-        int p = dir > 0 ? r : M - 1 - r;
+        int q = dir > 0 ? r : M - 1 - r;
         if (periodic) {
-            p %= M;
-            if (p < 0) p += M;
+            q %= M;
+            if (q < 0) q += M;
         }
-        phys = p;
+        phys = q;
     }
+    // Each row address is computed from the row index (no running pointer):
+    // the loads of an unrolled walk stay independent of each other and of
+    // the wrap selects, so they can all be issued early.
     __device__ void next(float* x)
     {
         if (periodic || (phys >= 0 && phys < M)) {
@@ -56,8 +59,38 @@ struct GlobalReader {
     }
 };
 
-// Writes frame row i of a strided line.  Scaled storage: the G lanes that
-// hold one uz-line (aligned groups) agree on its largest |value|.
+// Largest value over aligned groups of G lanes (G a power of two <= 64), in
+// every lane of the group: DPP quad permutations and row mirrors within a
+// 16-lane row, a swizzle across 32, a permute across 64.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        __builtin_bit_cast(int, v), __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float group_max(float m, int G)
+{
+    // every step runs; the group size only selects whether the partner's
+    // value counts (branch-free, so unrolled walks keep one basic block)
+    float q;
+    q = dpp_mov<0xB1>(m);                          // quad_perm [1,0,3,2]
+    m = fmaxf(m, G >= 2 ? q : m);
+    q = dpp_mov<0x4E>(m);                          // quad_perm [2,3,0,1]
+    m = fmaxf(m, G >= 4 ? q : m);
+    q = dpp_mov<0x141>(m);                         // row_half_mirror
+    m = fmaxf(m, G >= 8 ? q : m);
+    q = dpp_mov<0x140>(m);                         // row_mirror
+    m = fmaxf(m, G >= 16 ? q : m);
+    // swizzle, bit mode: lane ^ 16 within each half of the wave
+    q = __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, m), 0x401F));
+    m = fmaxf(m, G >= 32 ? q : m);
+    q = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(
+            (int)((threadIdx.x ^ 32) & 63) << 2, __builtin_bit_cast(int, m)));
+    m = fmaxf(m, G >= 64 ? q : m);
+    return m;
+}
+
 template <int P, int V>
 struct GlobalWriter {
     using T = typename Codec<P>::T;
@@ -71,17 +104,17 @@ struct GlobalWriter {
 
     __device__ void put(int i, const float* x)
     {
-        const int p = dir > 0 ? i : M - 1 - i;
+        const long p = dir > 0 ? i : M - 1 - i;
         if (Codec<P>::scaled) {
             float m = 0.0f;
 #pragma unroll
             for (int v = 0; v < V; ++v) m = fmaxf(m, fabsf(x[v]));
-            for (int w = 1; w < G; w <<= 1) m = fmaxf(m, __shfl_xor(m, w));
-            const float inv = m > 0.0f ? 1.0f / m : 0.0f;
-            store_row<P, V>(base + (long)p * stride, x, inv);
-            if ((threadIdx.x & (G - 1)) == 0) sbase[(long)p * sstride] = m;
+            m = group_max(m, G);
+            const float inv = inv_scale(m);
+            store_row<P, V>(base + p * stride, x, inv);
+            if ((threadIdx.x & (G - 1)) == 0) sbase[p * sstride] = m;
         } else {
-            store_row<P, V>(base + (long)p * stride, x, 1.0f);
+            store_row<P, V>(base + p * stride, x, 1.0f);
         }
     }
 };

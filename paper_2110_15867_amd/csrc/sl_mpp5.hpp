@@ -40,6 +40,13 @@ template <> struct Codec<PREC_BF16> {
 
 template <typename T, int V> struct alignas(sizeof(T) * V) Pack { T v[V]; };
 
+// Inverse of a line scale (0 for an all-zero line): the hardware reciprocal,
+// used by every kernel that encodes, so all of them produce the same codes.
+__device__ __forceinline__ float inv_scale(float m)
+{
+    return m > 0.0f ? __builtin_amdgcn_rcpf(m) : 0.0f;
+}
+
 // Code of value x with inverse scale inv: the FP32 product, rounded once to
 // FP32, then rounded to the storage type.  The empty asm pins the FP32
 // product so instruction selection cannot merge the multiply into a
@@ -261,14 +268,14 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
     ra.next(xm2); ra.next(xm1); ra.next(x0); ra.next(xp1); ra.next(xp2);
     if (!periodic) {
         // rows already in the window that lie past the upper face
+        auto past = [&](int row) { return row >= M - N && row < M; };
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            const int row = r + q;
-            if (row >= M - N && row < M) {
-                const float* src = q == 0 ? xm2 : q == 1 ? xm1 : q == 2 ? x0 : q == 3 ? xp1 : xp2;
-#pragma unroll
-                for (int v = 0; v < V; ++v) acc += src[v];
-            }
+        for (int v = 0; v < V; ++v) {
+            acc += past(r) ? xm2[v] : 0.0f;
+            acc += past(r + 1) ? xm1[v] : 0.0f;
+            acc += past(r + 2) ? x0[v] : 0.0f;
+            acc += past(r + 3) ? xp1[v] : 0.0f;
+            acc += past(r + 4) ? xp2[v] : 0.0f;
         }
     }
     if (MT > 0 && periodic) {
@@ -291,7 +298,8 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
         xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v];
         dm2[v] = dm1[v]; dm1[v] = d0[v]; d0[v] = dp1[v];
     }
-#pragma unroll(MT > 0 ? MT : 1)
+    constexpr int UNR = MT > 0 ? MT : 1;
+#pragma unroll UNR
     for (int i = 0; i < M; ++i) {
         // new row j+2 for j = i - N
         if (MT > 0 && periodic && i >= M - 5) {
@@ -397,7 +405,8 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
         q0[v] = q1[v]; q1[v] = q2[v]; q2[v] = q3[v]; q3[v] = q4[v];
     }
     const float sgn = neg ? -1.0f : 1.0f;
-#pragma unroll(MT > 0 ? MT : 1)
+    constexpr int UNR = MT > 0 ? MT : 1;
+#pragma unroll UNR
     for (int i = 0; i < M; ++i) {
         if (MT > 0 && i >= M - 6) {
 #pragma unroll

@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(NT) k_vel_uz(const typename Codec<P>::T* __res
                 float m = 0.0f;
 #pragma unroll
                 for (int i = 0; i < MT; ++i) m = fmaxf(m, fabsf(wr.out[i]));
-                inv = m > 0.0f ? 1.0f / m : 0.0f;
+                inv = inv_scale(m);
                 sout[gline + threadIdx.x] = m;
             }
             float* line = tile + threadIdx.x * LS;
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) k_vel_uz_generic(const typename Codec<P>:
             ScaledReader srd{rd, sc};
             MaxWriter mw{0.0f};
             walk_uniform<1, 0>(srd, mw, M, sh, a.periodic, &ofl);
-            inv = mw.m > 0.0f ? 1.0f / mw.m : 0.0f;
+            inv = inv_scale(mw.m);
             sout[line] = mw.m;
             ScaledReader srd2{rd, sc};
             ContigWriter<P> cw{fout + line * M, M, dir, inv};
