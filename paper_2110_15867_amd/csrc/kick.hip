@@ -41,28 +41,76 @@ __device__ __forceinline__ void storage_round_line(float* line)
     for (int i = 0; i < NZ; ++i) line[i] = Codec<P>::dec(quantize<P>(x[i], inv)) * m;
 }
 
-template <int P, int NX, int NY, int NZ>
-__global__ void __launch_bounds__(NY * NZ) k_kick(const typename Codec<P>::T* __restrict__ fin,
+// A work-group-uniform value moved to a scalar register.  The empty asm hides
+// the value's uniformity, so the optimiser keeps the readfirstlane (it drops
+// one applied to a value it already knows to be uniform, which can leave the
+// value in a vector register and the address arithmetic on the VALU).
+__device__ __forceinline__ int uniform_sgpr(int v)
+{
+    asm volatile("" : "+v"(v));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Writes the updated line y (frame order) at its translated positions
+// out_{j+N} = y_j, frame position p at lds[b + p * st].  Vacuum lines: the
+// cells the translation empties become zero and what passes the upper face
+// is added to *acc; periodic lines wrap.
+template <int M, bool PER>
+__device__ __forceinline__ void put_translated(float* lds, int b, int st, const float (&y)[M],
+                                               int N, float scale, float* acc)
+{
+    if (PER) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            int p = j + N;                          // N < M for periodic lines
+            p = p >= M ? p - M : p;
+            lds[b + p * st] = y[j] * scale;
+        }
+    } else {
+        const int nz = N < M ? N : M;
+        for (int i = 0; i < nz; ++i) lds[b + i * st] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const int p = j + N;
+            if (p < M) lds[b + p * st] = y[j] * scale;
+            else *acc += y[j];
+        }
+    }
+}
+
+template <int M, bool PER>
+__device__ __forceinline__ float kept_max(const float (&y)[M], int N)
+{
+    float m = 0.0f;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        if (PER || j + N < M) m = fmaxf(m, fabsf(y[j]));
+    }
+    return m;
+}
+
+template <int P, int NU, bool PER>
+__global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __restrict__ fin,
                                                 const float* __restrict__ sin,
                                                 typename Codec<P>::T* __restrict__ fout,
                                                 float* __restrict__ sout, KickArgs a)
 {
-    static_assert(NX * NZ == NY * NZ && NX * NY == NY * NZ, "cubic velocity blocks only");
     using T = typename Codec<P>::T;
-    constexpr int NT = NY * NZ;
-    constexpr int LS = NZ + 1;
-    constexpr int NL = NX * NY;                 // uz-lines per cell
-    constexpr int NU = NX * NY * NZ;
+    constexpr int M = NU;
+    constexpr int NT = NU * NU;
+    constexpr int LS = NU + 1;
+    constexpr int NL = NU * NU;                 // uz-lines per cell
+    constexpr int NV = NU * NU * NU;
     extern __shared__ float lds[];
     __shared__ double red[NT / 64];
     const long cell = blockIdx.x;
     const int t = threadIdx.x;
 
     // ---- load the velocity block (coalesced 4-value accesses) ----
-    const T* src = fin + cell * NU;
-    for (int e = t * 4; e < NU; e += NT * 4) {
-        const int ln = e / NZ;
-        const int jz = e - ln * NZ;
+    const T* src = fin + cell * NV;
+    for (int e = t * 4; e < NV; e += NT * 4) {
+        const int ln = e / NU;
+        const int jz = e - ln * NU;
         const float sc = Codec<P>::scaled ? sin[cell * NL + ln] : 1.0f;
         float x[4];
         load_row<P, 4>(src + e, sc, x);
@@ -74,65 +122,65 @@ __global__ void __launch_bounds__(NY * NZ) k_kick(const typename Codec<P>::T* __
     double tot[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int axis = 0; axis < 3; ++axis) {
-        const int M = axis == 0 ? NX : (axis == 1 ? NY : NZ);
         const double s = (double)a.g[(long)axis * a.cells + cell] * a.factor[axis];
-        const LineShift sh = split_shift(s, M, a.periodic);
-        const int dir = sh.neg ? -1 : 1;
+        const LineShift sh = split_shift(s, M, PER);
         // line of this thread and the LDS stride along the axis
         int base, stride;
         if (axis == 0) {            // lines (jy, jz) along jx
-            base = (t / NZ) * LS + (t % NZ);
-            stride = NY * LS;
+            base = (t / NU) * LS + (t % NU);
+            stride = NU * LS;
         } else if (axis == 1) {     // lines (jx, jz) along jy
-            base = (t / NZ) * NY * LS + (t % NZ);
+            base = (t / NU) * NU * LS + (t % NU);
             stride = LS;
         } else {                    // lines (jx, jy) along jz
             base = t * LS;
             stride = 1;
         }
-        RegWriter<NX> wr;           // NX == NY == NZ
-        float ofl = 0.0f;
-        LdsReader rd{lds + base, stride, M, dir, a.periodic, 0};
-        walk_uniform<1, NX>(rd, wr, M, sh, a.periodic, &ofl);
-        tot[axis] = (double)ofl;
+        // upwind frame: frame position p sits at lds[b + p * st]
+        // (the shift is uniform over the work-group: N and st live in SGPRs,
+        // so the translated store addresses cost scalar arithmetic only)
+        const int N = uniform_sgpr(sh.N);
+        const int st = uniform_sgpr(sh.neg ? -stride : stride);
+        const int b = sh.neg ? base + (M - 1) * stride : base;
+        float x[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) x[k] = lds[b + k * st];
         __syncthreads();            // every line read before any is overwritten
-        if (axis < 2) {
-#pragma unroll
-            for (int i = 0; i < NX; ++i) lds[base + (dir > 0 ? i : NX - 1 - i) * stride] = wr.out[i];
-            if (Codec<P>::scaled) {
-                __syncthreads();
-                storage_round_line<P, NZ>(lds + t * LS);
-            }
+        float y[M];
+        float phi_top;
+        line_update_regs<M, PER>(x, sh, y, &phi_top);
+        float acc = 0.0f;
+        if (axis < 2 || !Codec<P>::scaled) {
+            put_translated<M, PER>(lds, b, st, y, N, 1.0f, &acc);
         } else {
-            float inv = 1.0f;
-            if (Codec<P>::scaled) {
-                float m = 0.0f;
-#pragma unroll
-                for (int i = 0; i < NZ; ++i) m = fmaxf(m, fabsf(wr.out[i]));
-                inv = inv_scale(m);
-                sout[cell * NL + t] = m;
-            }
-#pragma unroll
-            for (int i = 0; i < NZ; ++i) lds[base + (dir > 0 ? i : NZ - 1 - i)] = wr.out[i] * inv;
+            // the last sweep leaves the values divided by the new line scale
+            const float m = kept_max<M, PER>(y, N);
+            sout[cell * NL + t] = m;
+            put_translated<M, PER>(lds, b, st, y, N, inv_scale(m), &acc);
         }
+        if (!PER) tot[axis] = (double)(acc + phi_top);
         __syncthreads();
+        if (Codec<P>::scaled && axis < 2) {
+            storage_round_line<P, NU>(lds + t * LS);
+            __syncthreads();
+        }
     }
 
     // ---- store (coalesced) ----
-    T* dst = fout + cell * NU;
-    for (int e = t * 4; e < NU; e += NT * 4) {
-        const int ln = e / NZ;
-        const int jz = e - ln * NZ;
+    T* dst = fout + cell * NV;
+    for (int e = t * 4; e < NV; e += NT * 4) {
+        const int ln = e / NU;
+        const int jz = e - ln * NU;
         Pack<T, 4> q;
 #pragma unroll
         for (int u = 0; u < 4; ++u) q.v[u] = Codec<P>::enc(lds[ln * LS + jz + u]);
         *reinterpret_cast<Pack<T, 4>*>(dst + e) = q;
     }
-    if (a.outflow != nullptr && !a.periodic) {
+    if (a.outflow != nullptr && !PER) {
         // same order as three separate sweeps: ux, then uy, then uz
         for (int axis = 0; axis < 3; ++axis) {
-            const double s = block_sum(tot[axis], red);
-            if (t == 0) a.outflow[cell] += s * a.du3;
+            const double sm = block_sum(tot[axis], red);
+            if (t == 0) a.outflow[cell] += sm * a.du3;
         }
     }
 }
@@ -143,7 +191,7 @@ static hipError_t launch_kick_n(const void* fin, const float* sin, void* fout, f
 {
     using T = typename Codec<P>::T;
     const size_t lds = (size_t)N * N * (N + 1) * sizeof(float);
-    auto kern = k_kick<P, N, N, N>;
+    auto kern = a.periodic ? k_kick<P, N, true> : k_kick<P, N, false>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -345,6 +345,50 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
     }
 }
 
+// ---------------------------------------------------------------------------
+// Whole-line update in registers: the line (compile-time length M) is already
+// held in x[0..M-1] in its upwind frame, so every cell of every stencil is a
+// fixed register and nothing waits on a load between interfaces.  Ghosts are
+// zero (vacuum) or the wrapped cells (PER).  Produces, in frame order,
+//   y_j = x_j - (Phi_{j+1/2} - Phi_{j-1/2}),   j = 0 .. M-1,
+// with the same FP32 operations as walk_uniform; the integer translation
+// out_{j+N} = y_j is left to the caller's stores.  *phi_top = Phi_{M-1/2},
+// the flux through the upper face before the translation.
+// ---------------------------------------------------------------------------
+template <int M, bool PER>
+__device__ __forceinline__ float line_cell(const float (&x)[M], int k)
+{
+    if (PER) return x[((k % M) + M) % M];
+    return (k >= 0 && k < M) ? x[k] : 0.0f;
+}
+
+template <int M, bool PER>
+__device__ __forceinline__ void line_update_regs(const float (&x)[M], const LineShift& sh,
+                                                 float (&y)[M], float* phi_top)
+{
+    auto X = [&](int k) { return line_cell<M, PER>(x, k); };
+    // Phi_{-1/2}: the interface below cell 0 (for PER the one at the top)
+    float phi_prev = 0.0f;
+    if (!PER) {
+        phi_prev = flux_mag(Stencil{X(-3), X(-2), X(-1), X(0), X(1), X(-2) - X(-3),
+                                    X(-1) - X(-2), X(0) - X(-1), X(1) - X(0)}, sh);
+    }
+    float dm2 = X(-1) - X(-2), dm1 = X(0) - X(-1), d0 = X(1) - X(0);
+    float phi_first = 0.0f;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const float dp1 = X(j + 2) - X(j + 1);
+        const float phi = flux_mag(Stencil{X(j - 2), X(j - 1), X(j), X(j + 1), X(j + 2), dm2, dm1,
+                                           d0, dp1}, sh);
+        if (PER && j == 0) phi_first = phi;
+        if (!PER || j > 0) y[j] = X(j) - (phi - phi_prev);
+        phi_prev = phi;
+        dm2 = dm1; dm1 = d0; d0 = dp1;
+    }
+    if (PER) y[0] = X(0) - (phi_first - phi_prev);   // Phi_{-1/2} = Phi_{M-1/2}
+    *phi_top = phi_prev;
+}
+
 // Upwind stencil of the interface j+1/2 from the window x_{j-2..j+3} and its
 // differences: as is for a rightward shift, mirrored (x_{j+3..j-1}, negated
 // differences in reverse order) for a leftward one.

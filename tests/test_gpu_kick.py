@@ -21,9 +21,11 @@ from paper_2110_15867_amd import vlasov as V  # noqa: E402
 @pytest.mark.parametrize("shape", [((3, 4, 5), (16, 16, 16)), ((2, 3, 3), (32, 32, 32)),
                                    ((2, 3, 2), (8, 8, 8))])
 @pytest.mark.parametrize("vbc", [V.VBC_OUTFLOW, V.VBC_PERIODIC])
-def test_kick_equals_three_sweeps(prec, shape, vbc):
+@pytest.mark.parametrize("cfl", [3.3, 45.0])
+def test_kick_equals_three_sweeps(prec, shape, vbc, cfl):
+    """cfl: largest |shift| in cells; 45 moves whole blocks out (vacuum) or wraps them."""
     n, nu = shape
-    print("case: kick", V.PREC_NAME[prec], n, nu, vbc, flush=True)
+    print("case: kick", V.PREC_NAME[prec], n, nu, vbc, cfl, flush=True)
     hg = V.make_grid(n, nu, (1.0, 1.0, 1.0), (1.0, 0.9, 1.1))
     rng = np.random.default_rng(5)
     f = torch.from_numpy(rng.uniform(0, 1, V.grid_shape(hg)).astype(np.float32) ** 2).cuda()
@@ -33,7 +35,7 @@ def test_kick_equals_three_sweeps(prec, shape, vbc):
     field = np.zeros((3, cells), np.float32)
     for a in range(3):
         du = 2 * hg.umax[a] / hg.nu[a]
-        field[a] = (rng.uniform(-3.3, 3.3, cells) * du / dt).astype(np.float32)
+        field[a] = (rng.uniform(-cfl, cfl, cells) * du / dt).astype(np.float32)
     g = torch.from_numpy(field.reshape((3,) + tuple(n))).cuda()
     o1 = torch.zeros(tuple(n), dtype=torch.float64, device="cuda")
     o2 = torch.zeros(tuple(n), dtype=torch.float64, device="cuda")
