@@ -105,15 +105,13 @@ struct FluxLin {
 // flux_mag / mp_bounded operation by operation.
 __device__ FluxLin flux_lin(const Stencil& s, const LineShift& sh, const WeightSlopes& ds)
 {
-    float fhat = sh.w0 * s.a;
-    fhat = fmaf(sh.w1, s.b, fhat);
-    fhat = fmaf(sh.w2, s.c, fhat);
-    fhat = fmaf(sh.w3, s.d, fhat);
-    fhat = fmaf(sh.w4, s.e, fhat);
+    float y = sh.v0 * s.dm2;
+    y = fmaf(sh.v1, s.dm1, y);
+    y = fmaf(sh.v2, s.d0, y);
+    y = fmaf(sh.v3, s.dp1, y);
     const float m = med3(s.d0, 4.0f * s.dm1, 0.0f);
-    const float y = fhat - s.c;
     VL L;
-    L.v = fhat;
+    L.v = s.c + y;
     L.l.w[0] = sh.w0; L.l.w[1] = sh.w1; L.l.w[2] = sh.w2; L.l.w[3] = sh.w3; L.l.w[4] = sh.w4;
     bool L_is_fhat = true;
     if (med3(y, 0.0f, m) != y) {

@@ -6,15 +6,22 @@
 // section 5.1.3), so a work-group can hold the whole block (32^3 FP32 values
 // = 128 KiB of MI355X's 160 KiB LDS), run ux, uy and uz on it, and touch HBM
 // once for reading and once for writing instead of three times each.  Each
-// sweep runs the same line walker with the same FP32 operations as the
-// single-sweep kernels, and with FP16/BF16 storage the intermediate results
-// are rounded exactly as if they had been stored, so the result is bitwise
-// the one of the three separate sweeps.
+// sweep performs the same FP32 operations as the single-sweep kernels, and
+// with FP16/BF16 storage the intermediate results are rounded exactly as if
+// they had been stored, so the result is bitwise the one of the three
+// separate sweeps.
 //
-// LDS layout: uz-lines of NZ values padded to NZ+1 floats, line index
-// jx*NY + jy.  A thread owns one line per sweep; lanes of a wave read
-// consecutive jz (ux, uy sweeps) or lines 33 floats apart (uz sweep), both
-// free of bank conflicts.
+// The work-groups are persistent (as many as fit on the chip, each walking
+// cells blockIdx.x, blockIdx.x + gridDim.x, ...).  While one block is swept
+// in LDS, the next one is already on its way from HBM into registers, and the
+// finished block's stores drain behind the next block's arithmetic: the LDS
+// holds one block, so this is the only way its HBM traffic overlaps compute.
+//
+// LDS layout: uz-lines of NU values padded to NU+1 floats, line index
+// jx*NU + jy.  A thread owns one line per sweep; lanes of a wave read
+// consecutive jz (ux, uy sweeps) or lines NU+1 floats apart (uz sweep), both
+// free of bank conflicts.  Lines of one sweep are disjoint, so a thread may
+// overwrite its own line as soon as it has read it.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -51,42 +58,181 @@ __device__ __forceinline__ int uniform_sgpr(int v)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Writes the updated line y (frame order) at its translated positions
-// out_{j+N} = y_j, frame position p at lds[b + p * st].  Vacuum lines: the
-// cells the translation empties become zero and what passes the upper face
-// is added to *acc; periodic lines wrap.
-template <int M, bool PER>
-__device__ __forceinline__ void put_translated(float* lds, int b, int st, const float (&y)[M],
-                                               int N, float scale, float* acc)
+__device__ __forceinline__ float uniform_f32(float v)
 {
-    if (PER) {
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            int p = j + N;                          // N < M for periodic lines
-            p = p >= M ? p - M : p;
-            lds[b + p * st] = y[j] * scale;
-        }
-    } else {
-        const int nz = N < M ? N : M;
-        for (int i = 0; i < nz; ++i) lds[b + i * st] = 0.0f;
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-            const int p = j + N;
-            if (p < M) lds[b + p * st] = y[j] * scale;
-            else *acc += y[j];
-        }
-    }
+    return __builtin_bit_cast(float, uniform_sgpr(__builtin_bit_cast(int, v)));
 }
 
-template <int M, bool PER>
-__device__ __forceinline__ float kept_max(const float (&y)[M], int N)
-{
-    float m = 0.0f;
+// One thread's share of a velocity block in flight from HBM: NS slots of 4
+// consecutive values of one uz-line, with that line's scale.
+template <int P, int NU>
+struct BlockSlots {
+    using T = typename Codec<P>::T;
+    static constexpr int NT = NU * NU;
+    static constexpr int NS = NU * NU * NU / (NT * 4);
+    Pack<T, 4> q[NS];
+    float sc[NS];
+    float g[3];        // the cell's acceleration field (ux, uy, uz)
+
+    // element index of slot s: consecutive threads take consecutive 4-value
+    // groups, so every access is coalesced
+    __device__ static int elem(int s, int t) { return (s * NT + t) * 4; }
+
+    // (t arrives through fresh_tid() at every use: the slot offsets are
+    // recomputed, a few integer operations, instead of occupying registers
+    // for the whole sweep)
+    __device__ void load(const T* __restrict__ fin, const float* __restrict__ sin,
+                         const KickArgs& a, int cell, int t)
+    {
+        // the field first: the sweeps wait for it, not for the block behind it
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        if (PER || j + N < M) m = fmaxf(m, fabsf(y[j]));
+        for (int k = 0; k < 3; ++k) g[k] = a.g[(long)k * a.cells + cell];
+        const T* src = fin + (long)cell * (NT * NU);
+        const float* ssrc = sin + (long)cell * NT;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int e = elem(s, t);
+            q[s] = *reinterpret_cast<const Pack<T, 4>*>(src + e);
+            sc[s] = Codec<P>::scaled ? ssrc[e / NU] : 1.0f;
+        }
     }
-    return m;
+    // decoded values into the padded LDS block
+    __device__ void put(float* lds, int t) const
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int e = elem(s, t);
+            float* dst = lds + (e / NU) * (NU + 1) + e % NU;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                dst[u] = Codec<P>::scaled ? Codec<P>::dec(q[s].v[u]) * sc[s] : Codec<P>::dec(q[s].v[u]);
+        }
+    }
+};
+
+// threadIdx.x, opaque to the optimiser (see BlockSlots)
+__device__ __forceinline__ int fresh_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+template <int M, int S, bool NEG>
+__device__ __forceinline__ void read_line(const float* line, float (&x)[M])
+{
+#pragma unroll
+    for (int k = 0; k < M; ++k) x[k] = line[(NEG ? M - 1 - k : k) * S];
+}
+
+// The integer part N > 0 of a line's shift, applied after the fractional
+// update has left y_j at frame position j: out_{j+N} = y_j.  Vacuum lines
+// return what passes the upper face, sum_{j >= M-N} y_j + Phi_{M-1/2};
+// periodic lines rotate.  (Rare in practice -- a kick moves less than one
+// cell per half step unless the field is strong -- so the addressing here is
+// plain runtime arithmetic.)
+template <int M, int S, bool NEG, bool PER>
+__device__ __forceinline__ float translate_line(float* line, int N, float phi_top)
+{
+    auto at = [&](int p) -> float& { return line[(NEG ? M - 1 - p : p) * S]; };
+    if (PER) {
+        float z[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) z[k] = at(k);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            int p = k + N;                     // N < M on periodic lines
+            p = p >= M ? p - M : p;
+            at(p) = z[k];
+        }
+        return 0.0f;
+    }
+    float acc = 0.0f;
+    for (int p = (M - N > 0 ? M - N : 0); p < M; ++p) acc += at(p);
+    for (int p = M - 1; p >= N; --p) at(p) = at(p - N);
+    const int nz = N < M ? N : M;
+    for (int p = 0; p < nz; ++p) at(p) = 0.0f;
+    return acc + phi_top;
+}
+
+// One velocity sweep of the block in LDS along AXIS (0: ux, 1: uy, 2: uz),
+// for lines whose upwind direction is -u (NEG) or +u: frame position p of a
+// line lies at line[(NEG ? M-1-p : p) * S], so every access of the common
+// case (|shift| < 1 cell) has a fixed offset.  Returns this thread's line
+// outflow (vacuum boundaries).  With scaled storage the uz sweep also finds
+// the new scale of its uz-line (the largest |value| it keeps) and writes it to
+// sout_line and lmax_line.
+template <int P, int NU, bool PER, int AXIS, bool NEG>
+__device__ __forceinline__ float kick_axis_dir(float* line, const LineShift& sh, int N,
+                                               float* sout_line, float* lmax_line)
+{
+    constexpr int M = NU;
+    constexpr int S = AXIS == 0 ? NU * (NU + 1) : (AXIS == 1 ? NU + 1 : 1);
+    constexpr bool SCALE = Codec<P>::scaled && AXIS == 2;
+    auto at = [&](int p) -> float& { return line[(NEG ? M - 1 - p : p) * S]; };
+    float x[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) x[k] = at(k);
+    float m = 0.0f;                              // largest |value| (uz sweep)
+    const float phi_top = line_update_regs<M, PER>(x, sh, [&](int j, float v) {
+        at(j) = v;                               // the line reads above came first
+        if (SCALE) m = fmaxf(m, fabsf(v));
+    });
+    float ofl = PER ? 0.0f : phi_top;            // N = 0: Phi_{M-1/2} leaves
+    if (N > 0) {
+        ofl = translate_line<M, S, NEG, PER>(line, N, phi_top);
+        if (SCALE && !PER) {
+            m = 0.0f;                            // only what stayed
+            for (int p = N; p < M; ++p) m = fmaxf(m, fabsf(at(p)));
+        }
+    }
+    if (SCALE) {
+        // the new scale of this uz-line; the store divides by it
+        *sout_line = m;
+        *lmax_line = m;
+    }
+    return ofl;
+}
+
+template <int P, int NU, bool PER, int AXIS>
+__device__ __forceinline__ float kick_axis(float* lds, float* sout_line, float* lmax_line,
+                                           const KickArgs& a, float g, int t)
+{
+    constexpr int LS = NU + 1;
+    const int base = AXIS == 0 ? (t / NU) * LS + (t % NU)
+                   : AXIS == 1 ? (t / NU) * NU * LS + (t % NU)
+                               : t * LS;
+    const LineShift sh = split_shift((double)g * a.factor[AXIS], NU, PER);
+    const int N = uniform_sgpr(sh.N);
+    if (uniform_sgpr(sh.neg ? 1 : 0))
+        return kick_axis_dir<P, NU, PER, AXIS, true>(lds + base, sh, N, sout_line, lmax_line);
+    return kick_axis_dir<P, NU, PER, AXIS, false>(lds + base, sh, N, sout_line, lmax_line);
+}
+
+// FP64 sums of three values per thread over the work-group (the tree of
+// block_sum for each), in thread 0.
+template <int NT>
+__device__ __forceinline__ void block_sum3(double (&v)[3], double* red)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        for (int w = 32; w >= 1; w >>= 1) v[k] += __shfl_xor(v[k], w);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) red[k * (NT / 64) + wave] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < NT / 64; ++q) s += red[k * (NT / 64) + q];
+            v[k] = s;
+        }
+    }
 }
 
 template <int P, int NU, bool PER>
@@ -96,106 +242,104 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
                                                 float* __restrict__ sout, KickArgs a)
 {
     using T = typename Codec<P>::T;
-    constexpr int M = NU;
+    using Slots = BlockSlots<P, NU>;
     constexpr int NT = NU * NU;
-    constexpr int LS = NU + 1;
     constexpr int NL = NU * NU;                 // uz-lines per cell
     constexpr int NV = NU * NU * NU;
     extern __shared__ float lds[];
-    __shared__ double red[NT / 64];
-    const long cell = blockIdx.x;
+    __shared__ double red[3 * (NT / 64)];
+    __shared__ float lmax[Codec<P>::scaled ? NL : 1];   // new uz-line scales
     const int t = threadIdx.x;
+    const int ncell = (int)a.cells;             // the launcher checks the range
+    int cell = blockIdx.x;
+    if (cell >= ncell) return;                  // uniform over the work-group
 
-    // ---- load the velocity block (coalesced 4-value accesses) ----
-    const T* src = fin + cell * NV;
-    for (int e = t * 4; e < NV; e += NT * 4) {
-        const int ln = e / NU;
-        const int jz = e - ln * NU;
-        const float sc = Codec<P>::scaled ? sin[cell * NL + ln] : 1.0f;
-        float x[4];
-        load_row<P, 4>(src + e, sc, x);
+    Slots R;
+    R.load(fin, sin, a, cell, fresh_tid());
+    R.put(lds, fresh_tid());
+    float g[3];                                 // field of the cell in LDS (scalar)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) lds[ln * LS + jz + q] = x[q];
-    }
+    for (int k = 0; k < 3; ++k) g[k] = uniform_f32(R.g[k]);
+    int next = uniform_sgpr(cell + (int)gridDim.x);
+    if (next < ncell) R.load(fin, sin, a, next, fresh_tid());
     __syncthreads();
 
-    double tot[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int axis = 0; axis < 3; ++axis) {
-        const double s = (double)a.g[(long)axis * a.cells + cell] * a.factor[axis];
-        const LineShift sh = split_shift(s, M, PER);
-        // line of this thread and the LDS stride along the axis
-        int base, stride;
-        if (axis == 0) {            // lines (jy, jz) along jx
-            base = (t / NU) * LS + (t % NU);
-            stride = NU * LS;
-        } else if (axis == 1) {     // lines (jx, jz) along jy
-            base = (t / NU) * NU * LS + (t % NU);
-            stride = LS;
-        } else {                    // lines (jx, jy) along jz
-            base = t * LS;
-            stride = 1;
-        }
-        // upwind frame: frame position p sits at lds[b + p * st]
-        // (the shift is uniform over the work-group: N and st live in SGPRs,
-        // so the translated store addresses cost scalar arithmetic only)
-        const int N = uniform_sgpr(sh.N);
-        const int st = uniform_sgpr(sh.neg ? -stride : stride);
-        const int b = sh.neg ? base + (M - 1) * stride : base;
-        float x[M];
-#pragma unroll
-        for (int k = 0; k < M; ++k) x[k] = lds[b + k * st];
-        __syncthreads();            // every line read before any is overwritten
-        float y[M];
-        float phi_top;
-        line_update_regs<M, PER>(x, sh, y, &phi_top);
-        float acc = 0.0f;
-        if (axis < 2 || !Codec<P>::scaled) {
-            put_translated<M, PER>(lds, b, st, y, N, 1.0f, &acc);
-        } else {
-            // the last sweep leaves the values divided by the new line scale
-            const float m = kept_max<M, PER>(y, N);
-            sout[cell * NL + t] = m;
-            put_translated<M, PER>(lds, b, st, y, N, inv_scale(m), &acc);
-        }
-        if (!PER) tot[axis] = (double)(acc + phi_top);
+    for (;;) {
+        float o[3];
+        o[0] = kick_axis<P, NU, PER, 0>(lds, nullptr, nullptr, a, g[0], t);
         __syncthreads();
-        if (Codec<P>::scaled && axis < 2) {
-            storage_round_line<P, NU>(lds + t * LS);
+        if (Codec<P>::scaled) {
+            storage_round_line<P, NU>(lds + t * (NU + 1));
             __syncthreads();
         }
-    }
-
-    // ---- store (coalesced) ----
-    T* dst = fout + cell * NV;
-    for (int e = t * 4; e < NV; e += NT * 4) {
-        const int ln = e / NU;
-        const int jz = e - ln * NU;
-        Pack<T, 4> q;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) q.v[u] = Codec<P>::enc(lds[ln * LS + jz + u]);
-        *reinterpret_cast<Pack<T, 4>*>(dst + e) = q;
-    }
-    if (a.outflow != nullptr && !PER) {
-        // same order as three separate sweeps: ux, then uy, then uz
-        for (int axis = 0; axis < 3; ++axis) {
-            const double sm = block_sum(tot[axis], red);
-            if (t == 0) a.outflow[cell] += sm * a.du3;
+        o[1] = kick_axis<P, NU, PER, 1>(lds, nullptr, nullptr, a, g[1], t);
+        __syncthreads();
+        if (Codec<P>::scaled) {
+            storage_round_line<P, NU>(lds + t * (NU + 1));
+            __syncthreads();
         }
+        o[2] = kick_axis<P, NU, PER, 2>(lds, Codec<P>::scaled ? sout + (long)cell * NL + t : nullptr,
+                                        lmax + t, a, g[2], t);
+        __syncthreads();
+
+        if (a.outflow != nullptr && !PER) {
+            // same order as three separate sweeps: ux, then uy, then uz
+            double v[3] = {(double)o[0], (double)o[1], (double)o[2]};
+            block_sum3<NT>(v, red);
+            if (t == 0) {
+                double acc = a.outflow[cell];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) acc += v[k] * a.du3;
+                a.outflow[cell] = acc;
+            }
+        }
+
+        // store the finished block; each slot is refilled with the next block
+        // by the thread that stored it, so no barrier sits in between
+        T* dst = fout + (long)cell * NV;
+        const int ts = fresh_tid();
+#pragma unroll
+        for (int s = 0; s < Slots::NS; ++s) {
+            const int e = Slots::elem(s, ts);
+            float* src = lds + (e / NU) * (NU + 1) + e % NU;
+            const float inv = Codec<P>::scaled ? inv_scale(lmax[e / NU]) : 1.0f;
+            Pack<T, 4> q;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q.v[u] = quantize<P>(src[u], inv);
+            *reinterpret_cast<Pack<T, 4>*>(dst + e) = q;
+        }
+        if (next >= ncell) break;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) g[k] = uniform_f32(R.g[k]);
+        R.put(lds, ts);
+        cell = next;
+        next = uniform_sgpr(cell + (int)gridDim.x);
+        if (next < ncell) R.load(fin, sin, a, next, fresh_tid());
+        __syncthreads();
     }
 }
 
-template <int P, int N>
-static hipError_t launch_kick_n(const void* fin, const float* sin, void* fout, float* sout,
+template <int P, int N, bool PER>
+static hipError_t launch_kick_t(const void* fin, const float* sin, void* fout, float* sout,
                                 const KickArgs& a, hipStream_t st)
 {
     using T = typename Codec<P>::T;
     const size_t lds = (size_t)N * N * (N + 1) * sizeof(float);
-    auto kern = a.periodic ? k_kick<P, N, true> : k_kick<P, N, false>;
+    auto kern = k_kick<P, N, PER>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)a.cells), dim3(N * N), lds, st, (const T*)fin, sin,
+    // persistent grid: as many work-groups as are resident at once
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
+                                                          N * N, lds)) != hipSuccess)
+        return e;
+    long grid = (long)cus * (per_cu > 0 ? per_cu : 1);
+    if (grid > a.cells) grid = a.cells;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(N * N), lds, st, (const T*)fin, sin,
                        (T*)fout, sout, a);
     return hipGetLastError();
 }
@@ -204,8 +348,12 @@ template <int P>
 static hipError_t launch_kick_p(const void* fin, const float* sin, void* fout, float* sout,
                                 const KickArgs& a, hipStream_t st)
 {
-    if (a.nu[0] == 32) return launch_kick_n<P, 32>(fin, sin, fout, sout, a, st);
-    return launch_kick_n<P, 16>(fin, sin, fout, sout, a, st);
+    if (a.nu[0] == 32) {
+        return a.periodic ? launch_kick_t<P, 32, true>(fin, sin, fout, sout, a, st)
+                          : launch_kick_t<P, 32, false>(fin, sin, fout, sout, a, st);
+    }
+    return a.periodic ? launch_kick_t<P, 16, true>(fin, sin, fout, sout, a, st)
+                      : launch_kick_t<P, 16, false>(fin, sin, fout, sout, a, st);
 }
 
 bool kick_supported(const int nu[3], size_t lds_limit)
@@ -220,6 +368,7 @@ hipError_t launch_kick(int prec, const void* fin, const float* sin, void* fout, 
                        const KickArgs& a, hipStream_t st)
 {
     if (a.cells == 0) return hipSuccess;
+    if (a.cells > 0x7fffffffL) return hipErrorInvalidValue;   // cell indices are int
     switch (prec) {
         case PREC_F16: return launch_kick_p<PREC_F16>(fin, sin, fout, sout, a, st);
         case PREC_BF16: return launch_kick_p<PREC_BF16>(fin, sin, fout, sout, a, st);

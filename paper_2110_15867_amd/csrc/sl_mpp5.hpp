@@ -91,6 +91,7 @@ struct LineShift {
     float mu;   // fractional part |nu| in [0,1)
     bool neg;   // s < 0: walk the line mirrored
     float w0, w1, w2, w3, w4;   // interface-value weights for cells j-2 .. j+2
+    float v0, v1, v2, v3;       // the same in difference form (see sl5_weights)
 };
 
 // Interface value of the conservative SL flux: the mean over the departure
@@ -106,6 +107,14 @@ __device__ __forceinline__ void sl5_weights(float mu, LineShift& sh)
     sh.w2 = (mu + 1.0f) * (mu + 2.0f) * ((6.0f * mu - 33.0f) * mu + 47.0f) * k;
     sh.w3 = -(mu - 1.0f) * (mu - 2.0f) * (mu - 3.0f) * (4.0f * mu + 9.0f) * k;
     sh.w4 = (m2 - 1.0f) * (mu - 2.0f) * (mu - 3.0f) * k;
+    // The weights sum to one (a constant line is reproduced), so the
+    // interface value is f_j plus a combination of the four differences
+    // around it:  fhat - f_j = v0 (f_{j-1}-f_{j-2}) + v1 (f_j-f_{j-1})
+    //                        + v2 (f_{j+1}-f_j) + v3 (f_{j+2}-f_{j+1}).
+    sh.v0 = -sh.w0;
+    sh.v1 = -(sh.w0 + sh.w1);
+    sh.v2 = sh.w3 + sh.w4;
+    sh.v3 = sh.w4;
 }
 
 __device__ __forceinline__ LineShift split_shift(double s, int M, bool periodic)
@@ -183,17 +192,18 @@ __device__ __forceinline__ float mp_bounded(float fhat, const Stencil& s)
 // lies inside [fmin, fmax], so with epsilon = 0 the test only skips work:
 // the curvatures and bounds are evaluated for the (rarer, and in smooth data
 // wave-coherent) interfaces that fail it.
+// The unlimited value is formed as f_j + (fhat - f_j) from the carried
+// differences (four products instead of five, and fhat - f_j is what the
+// test needs).
 __device__ __forceinline__ float flux_mag(const Stencil& s, const LineShift& sh)
 {
-    float fhat = sh.w0 * s.a;
-    fhat = fmaf(sh.w1, s.b, fhat);
-    fhat = fmaf(sh.w2, s.c, fhat);
-    fhat = fmaf(sh.w3, s.d, fhat);
-    fhat = fmaf(sh.w4, s.e, fhat);
+    float y = sh.v0 * s.dm2;                            // fhat - f_j
+    y = fmaf(sh.v1, s.dm1, y);
+    y = fmaf(sh.v2, s.d0, y);
+    y = fmaf(sh.v3, s.dp1, y);
     const float m = med3(s.d0, 4.0f * s.dm1, 0.0f);     // f_MP - f_j
-    const float y = fhat - s.c;
-    float lim = fhat;
-    if (__builtin_expect(med3(y, 0.0f, m) != y, 0)) lim = mp_bounded(fhat, s);
+    float lim = s.c + y;
+    if (__builtin_expect(med3(y, 0.0f, m) != y, 0)) lim = mp_bounded(lim, s);
     // positivity: what leaves the upwind cell lies between 0 and its content
     return med3(sh.mu * lim, 0.0f, s.c);
 }
@@ -349,11 +359,12 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
 // Whole-line update in registers: the line (compile-time length M) is already
 // held in x[0..M-1] in its upwind frame, so every cell of every stencil is a
 // fixed register and nothing waits on a load between interfaces.  Ghosts are
-// zero (vacuum) or the wrapped cells (PER).  Produces, in frame order,
+// zero (vacuum) or the wrapped cells (PER).  Hands each result
 //   y_j = x_j - (Phi_{j+1/2} - Phi_{j-1/2}),   j = 0 .. M-1,
-// with the same FP32 operations as walk_uniform; the integer translation
-// out_{j+N} = y_j is left to the caller's stores.  *phi_top = Phi_{M-1/2},
-// the flux through the upper face before the translation.
+// to emit(j, y_j) as soon as it is known (for PER, y_0 comes last), with the
+// same FP32 operations as walk_uniform; the integer translation
+// out_{j+N} = y_j is the caller's.  Returns Phi_{M-1/2}, the flux through
+// the upper face before the translation.
 // ---------------------------------------------------------------------------
 template <int M, bool PER>
 __device__ __forceinline__ float line_cell(const float (&x)[M], int k)
@@ -362,9 +373,9 @@ __device__ __forceinline__ float line_cell(const float (&x)[M], int k)
     return (k >= 0 && k < M) ? x[k] : 0.0f;
 }
 
-template <int M, bool PER>
-__device__ __forceinline__ void line_update_regs(const float (&x)[M], const LineShift& sh,
-                                                 float (&y)[M], float* phi_top)
+template <int M, bool PER, class Emit>
+__device__ __forceinline__ float line_update_regs(const float (&x)[M], const LineShift& sh,
+                                                  Emit&& emit)
 {
     auto X = [&](int k) { return line_cell<M, PER>(x, k); };
     // Phi_{-1/2}: the interface below cell 0 (for PER the one at the top)
@@ -381,12 +392,12 @@ __device__ __forceinline__ void line_update_regs(const float (&x)[M], const Line
         const float phi = flux_mag(Stencil{X(j - 2), X(j - 1), X(j), X(j + 1), X(j + 2), dm2, dm1,
                                            d0, dp1}, sh);
         if (PER && j == 0) phi_first = phi;
-        if (!PER || j > 0) y[j] = X(j) - (phi - phi_prev);
+        if (!PER || j > 0) emit(j, X(j) - (phi - phi_prev));
         phi_prev = phi;
         dm2 = dm1; dm1 = d0; d0 = dp1;
     }
-    if (PER) y[0] = X(0) - (phi_first - phi_prev);   // Phi_{-1/2} = Phi_{M-1/2}
-    *phi_top = phi_prev;
+    if (PER) emit(0, X(0) - (phi_first - phi_prev));   // Phi_{-1/2} = Phi_{M-1/2}
+    return phi_prev;
 }
 
 // Upwind stencil of the interface j+1/2 from the window x_{j-2..j+3} and its
