@@ -48,21 +48,6 @@ __device__ __forceinline__ void storage_round_line(float* line)
     for (int i = 0; i < NZ; ++i) line[i] = Codec<P>::dec(quantize<P>(x[i], inv)) * m;
 }
 
-// A work-group-uniform value moved to a scalar register.  The empty asm hides
-// the value's uniformity, so the optimiser keeps the readfirstlane (it drops
-// one applied to a value it already knows to be uniform, which can leave the
-// value in a vector register and the address arithmetic on the VALU).
-__device__ __forceinline__ int uniform_sgpr(int v)
-{
-    asm volatile("" : "+v"(v));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-__device__ __forceinline__ float uniform_f32(float v)
-{
-    return __builtin_bit_cast(float, uniform_sgpr(__builtin_bit_cast(int, v)));
-}
-
 // One thread's share of a velocity block in flight from HBM: NS slots of 4
 // consecutive values of one uz-line, with that line's scale.
 template <int P, int NU>

@@ -91,7 +91,32 @@ __device__ __forceinline__ float group_max(float m, int G)
     return m;
 }
 
-template <int P, int V>
+// The same for a group size fixed at compile time, on values >= 0: their
+// IEEE bit patterns order like unsigned integers, so each step is a single
+// v_max_u32 with a DPP operand (no canonicalising of DPP results, no select).
+template <int CTRL>
+__device__ __forceinline__ unsigned dpp_mov_u(unsigned v)
+{
+    // old = 0 (the identity of max) lets the move fold into v_max_u32_dpp
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, true);
+}
+
+template <int G>
+__device__ __forceinline__ float group_max_nonneg(float m)
+{
+    unsigned u = __builtin_bit_cast(unsigned, m);
+    if (G >= 2) u = max(u, dpp_mov_u<0xB1>(u));       // quad_perm [1,0,3,2]
+    if (G >= 4) u = max(u, dpp_mov_u<0x4E>(u));       // quad_perm [2,3,0,1]
+    if (G >= 8) u = max(u, dpp_mov_u<0x141>(u));      // row_half_mirror
+    if (G >= 16) u = max(u, dpp_mov_u<0x140>(u));     // row_mirror
+    if (G >= 32) u = max(u, (unsigned)__builtin_amdgcn_ds_swizzle((int)u, 0x401F));
+    if (G >= 64)
+        u = max(u, (unsigned)__builtin_amdgcn_ds_bpermute((int)((threadIdx.x ^ 32) & 63) << 2, (int)u));
+    return __builtin_bit_cast(float, u);
+}
+
+// GC: lanes per uz-line when known at compile time (0: use the runtime G).
+template <int P, int V, int GC = 0>
 struct GlobalWriter {
     using T = typename Codec<P>::T;
     T* base;
@@ -109,12 +134,79 @@ struct GlobalWriter {
             float m = 0.0f;
 #pragma unroll
             for (int v = 0; v < V; ++v) m = fmaxf(m, fabsf(x[v]));
-            m = group_max(m, G);
+            m = GC > 0 ? group_max_nonneg<GC>(m) : group_max(m, G);
             const float inv = inv_scale(m);
             store_row<P, V>(base + p * stride, x, inv);
             if ((threadIdx.x & (G - 1)) == 0) sbase[p * sstride] = m;
         } else {
             store_row<P, V>(base + p * stride, x, 1.0f);
+        }
+    }
+};
+
+// Rows of the lines of one wave when every lane visits the same rows (one
+// integer shift and one walk direction over the wave; periodic lines): the
+// row index and the row's address are scalar work, and a lane only adds its
+// fixed 32-bit offset within the row, so no row access costs vector address
+// arithmetic.
+template <int P, int V>
+struct URowReader {
+    using T = typename Codec<P>::T;
+    const T* base;        // row 0 of the wave's first element (uniform)
+    const float* sbase;   // its scale (uniform; scaled storage)
+    unsigned loff;        // this lane's element offset within a row
+    unsigned soff;        // this lane's scale offset within a row
+    long stride;          // elements between rows
+    long sstride;         // scales between rows
+    int M;
+    int dir;              // uniform
+    int phys;             // uniform
+
+    __device__ void seek(int r)
+    {
+        int q = dir > 0 ? r : M - 1 - r;
+        q %= M;
+        if (q < 0) q += M;
+        phys = q;
+    }
+    __device__ void next(float* x)
+    {
+        const T* row = base + (long)phys * stride;
+        const float sc = Codec<P>::scaled ? (sbase + (long)phys * sstride)[soff] : 1.0f;
+        load_row<P, V>(row + loff, sc, x);
+        phys += dir;
+        if (phys == M) phys = 0;
+        else if (phys < 0) phys = M - 1;
+    }
+};
+
+template <int P, int V, int GC = 0>
+struct URowWriter {
+    using T = typename Codec<P>::T;
+    T* base;
+    float* sbase;
+    unsigned loff;
+    unsigned soff;
+    long stride;
+    long sstride;
+    int M;
+    int dir;              // uniform
+    int G;                // lanes per uz-line (scaled storage)
+
+    __device__ void put(int i, const float* x)
+    {
+        const long p = dir > 0 ? i : M - 1 - i;
+        T* row = base + p * stride;
+        if (Codec<P>::scaled) {
+            float m = 0.0f;
+#pragma unroll
+            for (int v = 0; v < V; ++v) m = fmaxf(m, fabsf(x[v]));
+            m = GC > 0 ? group_max_nonneg<GC>(m) : group_max(m, G);
+            const float inv = inv_scale(m);
+            store_row<P, V>(row + loff, x, inv);
+            if ((threadIdx.x & (G - 1)) == 0) (sbase + p * sstride)[soff] = m;
+        } else {
+            store_row<P, V>(row + loff, x, 1.0f);
         }
     }
 };

@@ -40,6 +40,21 @@ template <> struct Codec<PREC_BF16> {
 
 template <typename T, int V> struct alignas(sizeof(T) * V) Pack { T v[V]; };
 
+// A wave-uniform value moved to a scalar register.  The empty asm hides
+// the value's uniformity, so the optimiser keeps the readfirstlane (it drops
+// one applied to a value it already knows to be uniform, which can leave the
+// value in a vector register and the address arithmetic on the VALU).
+__device__ __forceinline__ int uniform_sgpr(int v)
+{
+    asm volatile("" : "+v"(v));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ float uniform_f32(float v)
+{
+    return __builtin_bit_cast(float, uniform_sgpr(__builtin_bit_cast(int, v)));
+}
+
 // Inverse of a line scale (0 for an all-zero line): the hardware reciprocal,
 // used by every kernel that encodes, so all of them produce the same codes.
 __device__ __forceinline__ float inv_scale(float m)
@@ -209,45 +224,41 @@ __device__ __forceinline__ float flux_mag(const Stencil& s, const LineShift& sh)
 }
 
 // ---------------------------------------------------------------------------
-// Read-ahead of a line: keeps PD rows in flight in a register ring so that
-// the loads of later rows overlap the flux arithmetic of earlier ones.  Rows
-// are fetched from the wrapped reader in order and never beyond `total`.
-// (PD = 1 is a plain pass-through, used when the line length is not known at
-// compile time and a register ring could not be indexed statically.)
+// Rows requested ahead of use.  With the line length known at compile time
+// a walk is fully unrolled, so the ring slot of every row is a constant and
+// the ring lives in registers: PD rows are in flight while the fluxes of
+// earlier rows are computed (HBM needs many bytes in flight per CU, and one
+// row of one wave is only 256 B-1 KiB).  The walks read rows strictly in
+// order; take(i) hands out the i-th row of the walk's loop and requests row
+// i + PD, never beyond the L rows the loop consumes.
 // ---------------------------------------------------------------------------
-template <int V, int PD, class Reader>
-struct ReadAhead {
-    Reader& rd;
-    float ring[PD][V];
-    int head;
-    int fetched;
-    int total;
-
-    __device__ ReadAhead(Reader& r, int tot) : rd(r), head(0), fetched(0), total(tot)
-    {
-#pragma unroll
-        for (int k = 0; k < PD; ++k) {
-            if (fetched < total) {
-                rd.next(ring[k]);
-                ++fetched;
-            }
-        }
-    }
-    __device__ void next(float* x)
-    {
-#pragma unroll
-        for (int v = 0; v < V; ++v) x[v] = ring[head][v];
-        if (fetched < total) {
-            rd.next(ring[head]);
-            ++fetched;
-        }
-        head = head + 1 == PD ? 0 : head + 1;
-    }
+template <int V, int MT>
+struct RowPipeDepth {
+    static constexpr int value = MT == 0 ? 1 : (V >= 2 ? 4 : 8);
 };
 
-template <int V, int MT>
-struct ReadAheadDepth {
-    static constexpr int value = 1;
+template <int V, int PD, class Reader>
+struct RowPipe {
+    Reader& rd;
+    float ring[PD][V];
+
+    __device__ explicit RowPipe(Reader& r) : rd(r) {}
+    __device__ void prime(int L)
+    {
+#pragma unroll
+        for (int q = 0; q < PD; ++q)
+            if (q < L) rd.next(ring[q]);
+    }
+    __device__ void take(int i, int L, float* x)
+    {
+        if (PD == 1) {
+            rd.next(x);
+            return;
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) x[v] = ring[i % PD][v];
+        if (i + PD < L) rd.next(ring[i % PD]);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -274,8 +285,11 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
     float acc = 0.0f;
     int r = -N - 3;                       // frame row of the next value
     rd.seek(r);
-    ReadAhead<V, ReadAheadDepth<V, MT>::value, Reader> ra(rd, (MT > 0 && periodic) ? M : M + 5);
-    ra.next(xm2); ra.next(xm1); ra.next(x0); ra.next(xp1); ra.next(xp2);
+    rd.next(xm2); rd.next(xm1); rd.next(x0); rd.next(xp1); rd.next(xp2);
+    // rows the loop reads (a periodic line's last five come from head[])
+    const int L = (MT > 0 && periodic) ? M - 5 : M;
+    RowPipe<V, RowPipeDepth<V, MT>::value, Reader> pipe(rd);
+    if (RowPipeDepth<V, MT>::value > 1) pipe.prime(L);
     if (!periodic) {
         // rows already in the window that lie past the upper face
         auto past = [&](int row) { return row >= M - N && row < M; };
@@ -316,7 +330,7 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
 #pragma unroll
             for (int v = 0; v < V; ++v) xp2[v] = head[i - (M - 5)][v];
         } else {
-            ra.next(xp2);
+            pipe.take(i, L, xp2);
         }
         if (!periodic) {
             if (r >= M - N && r < M) {
@@ -437,8 +451,10 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
     float q0[V], q1[V], q2[V], q3[V], q4[V];   // x_{j-1}-x_{j-2}, ..., x_{j+3}-x_{j+2}
     float head[6][V];
     rd.seek(-Ns - 3);
-    ReadAhead<V, ReadAheadDepth<V, MT>::value, Reader> ra(rd, MT > 0 ? M : M + 6);
-    ra.next(xm2); ra.next(xm1); ra.next(x0); ra.next(xp1); ra.next(xp2); ra.next(xp3);
+    rd.next(xm2); rd.next(xm1); rd.next(x0); rd.next(xp1); rd.next(xp2); rd.next(xp3);
+    const int L = MT > 0 ? M - 6 : M;           // rows the loop reads
+    RowPipe<V, RowPipeDepth<V, MT>::value, Reader> pipe(rd);
+    if (RowPipeDepth<V, MT>::value > 1) pipe.prime(L);
     if (MT > 0) {
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -467,7 +483,7 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
 #pragma unroll
             for (int v = 0; v < V; ++v) xp3[v] = head[i - (M - 6)][v];
         } else {
-            ra.next(xp3);
+            pipe.take(i, L, xp3);
         }
         float res[V];
 #pragma unroll

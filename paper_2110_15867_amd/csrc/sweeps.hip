@@ -1,309 +1,28 @@
-// Sweep kernels of the split SL-MPP5 Vlasov solver for gfx950.
-//
-// Layout f[ix][iy][iz][jx][jy][jz] (jz fastest).  A line along axis l is
-// addressed as (o * M + i) * I + k: o runs over the axes before l, i along l,
-// k over the axes after l ("inner", contiguous).  Three kernel families:
-//
-//  * k_position   x, y, z (Eq. 3).  One thread per V adjacent inner indices;
-//                 neighbouring lanes read neighbouring addresses of the same
-//                 row, so every row access is coalesced without a transpose.
-//                 The shift follows the velocity index along l.  Waves whose
-//                 lanes all move the same way use the mirrored 5-cell walker;
-//                 waves with both signs (the z sweep, shift set by the
-//                 contiguous u_z index) use the 6-cell walker with selects.
-//  * k_vel_strided ux, uy (Eq. 4).  One work-group per spatial cell: the
-//                 shift is g(x) dt / du, uniform over the velocity block, so
-//                 the walk direction and row addresses are wave-uniform.
-//                 The outflow through the velocity faces is reduced per cell
-//                 in FP64 in a fixed order.
-//  * k_vel_uz     uz.  The lines are contiguous (nu_z values), the case the
-//                 paper solves with its load-and-transpose (section 5.3): a
-//                 work-group loads a tile of whole lines with coalesced
-//                 16-byte loads into LDS, each thread walks one line out of
-//                 LDS, results go back through LDS and leave coalesced.
-//
-// Storage FP32, or FP16/BF16 codes with one FP32 scale per uz-line; the
-// scale of an output line is the largest |value| of that line, reduced
-// across the lanes that hold it.
+// Storage-precision dispatch of the sweep launchers (the kernels live in
+// sweeps_impl.hpp, instantiated per precision by sweeps_f32/f16/bf16.hip).
 #include <hip/hip_runtime.h>
-#include <stdint.h>
 
 #include "launch.hpp"
-#include "rows.hpp"
 #include "sl_mpp5.hpp"
 
 namespace vlasov {
 
-// ---------------------------------------------------------------------------
-// Position sweeps
-// ---------------------------------------------------------------------------
-template <int P, int V, int MT>
-__global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __restrict__ fin,
-                                                  const float* __restrict__ sin,
-                                                  typename Codec<P>::T* __restrict__ fout,
-                                                  float* __restrict__ sout, PosArgs a)
-{
-    const long IV = a.I / V;
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long total = a.O * IV;
-    if (t >= total) return;
-    const long o = t / IV;
-    const long k = (t - o * IV) * V;
-    const int M = MT > 0 ? MT : a.M;
-    const int jl = (int)(((k % a.Nu) / a.pst) % a.nshift);
-    const LineShift sh = split_shift(a.shift[jl], M, true);
-
-    const long lbase = o * (long)M * a.I + k;
-    const long sI = a.I / a.nuz;                 // uz-lines per row
-    const long sb = o * (long)M * sI + k / a.nuz;
-
-    const unsigned long long neg_lanes = __ballot(sh.neg);
-    const unsigned long long act = __ballot(1);
-    if (neg_lanes == 0 || neg_lanes == act) {
-        const int dir = sh.neg ? -1 : 1;
-        GlobalReader<P, V> rd{fin + lbase, sin + (Codec<P>::scaled ? sb : 0), a.I, sI, M, dir, true, 0};
-        GlobalWriter<P, V> wr{fout + lbase, sout + (Codec<P>::scaled ? sb : 0), a.I, sI, M, dir, a.G};
-        walk_uniform<V, MT>(rd, wr, M, sh, true, nullptr);
-    } else {
-        GlobalReader<P, V> rd{fin + lbase, sin + (Codec<P>::scaled ? sb : 0), a.I, sI, M, 1, true, 0};
-        GlobalWriter<P, V> wr{fout + lbase, sout + (Codec<P>::scaled ? sb : 0), a.I, sI, M, 1, a.G};
-        walk_mixed<V, MT>(rd, wr, M, sh.neg ? -sh.N : sh.N, sh);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Velocity sweeps ux, uy: one work-group per spatial cell
-// ---------------------------------------------------------------------------
-template <int P, int V, int MT>
-__global__ void __launch_bounds__(256) k_vel_strided(const typename Codec<P>::T* __restrict__ fin,
-                                                     const float* __restrict__ sin,
-                                                     typename Codec<P>::T* __restrict__ fout,
-                                                     float* __restrict__ sout, VelArgs a)
-{
-    __shared__ double red[4];
-    const long cell = blockIdx.x;
-    const int M = MT > 0 ? MT : a.M;
-    const double s = (double)a.g[cell] * a.factor;
-    const LineShift sh = split_shift(s, M, a.periodic);
-    const int dir = sh.neg ? -1 : 1;
-    const long IV = a.I / V;
-    const long lpc = (long)a.nsub * IV;
-    const long sI = a.I / a.nuz;
-    double mine = 0.0;
-    for (long l = threadIdx.x; l < lpc; l += blockDim.x) {
-        const long sub = l / IV;
-        const long k = (l - sub * IV) * V;
-        const long o = cell * a.nsub + sub;
-        const long lbase = o * (long)M * a.I + k;
-        const long sb = o * (long)M * sI + k / a.nuz;
-        GlobalReader<P, V> rd{fin + lbase, sin + (Codec<P>::scaled ? sb : 0), a.I, sI, M, dir, a.periodic, 0};
-        GlobalWriter<P, V> wr{fout + lbase, sout + (Codec<P>::scaled ? sb : 0), a.I, sI, M, dir, a.G};
-        float ofl = 0.0f;
-        walk_uniform<V, MT>(rd, wr, M, sh, a.periodic, &ofl);
-        mine += (double)ofl;
-    }
-    if (a.outflow != nullptr && !a.periodic) {
-        const double tot = block_sum(mine, red);
-        if (threadIdx.x == 0) a.outflow[cell] += tot * a.du3;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Velocity sweep uz: contiguous lines staged through LDS
-// ---------------------------------------------------------------------------
-template <int P, int MT, int NT>
-__global__ void __launch_bounds__(NT) k_vel_uz(const typename Codec<P>::T* __restrict__ fin,
-                                              const float* __restrict__ sin,
-                                              typename Codec<P>::T* __restrict__ fout,
-                                              float* __restrict__ sout, VelArgs a)
-{
-    using T = typename Codec<P>::T;
-    constexpr int LS = MT + 1;                  // padded line stride in LDS
-    __shared__ float tile[NT * LS];
-    __shared__ double red[NT / 64];
-    const long cell = blockIdx.x;
-    const double s = (double)a.g[cell] * a.factor;
-    const LineShift sh = split_shift(s, MT, a.periodic);
-    const int dir = sh.neg ? -1 : 1;
-    const long lpc = a.nsub;                    // lines per cell = nux * nuy
-    const long cbase = cell * lpc;              // first line of the cell
-    double mine = 0.0;
-    for (long l0 = 0; l0 < lpc; l0 += NT) {
-        const int nl = (int)((lpc - l0) < NT ? (lpc - l0) : NT);
-        const long gline = cbase + l0;
-        // coalesced load of nl whole lines, 4 values per access
-        const T* src = fin + gline * MT;
-        for (int e = threadIdx.x * 4; e < nl * MT; e += NT * 4) {
-            const int ln = e / MT;
-            const int off = e - ln * MT;
-            const float sc = Codec<P>::scaled ? sin[gline + ln] : 1.0f;
-            float x[4];
-            load_row<P, 4>(src + e, sc, x);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) tile[ln * LS + off + q] = x[q];
-        }
-        __syncthreads();
-        RegWriter<MT> wr;
-        float ofl = 0.0f;
-        if (threadIdx.x < nl) {
-            LdsReader rd{tile + threadIdx.x * LS, 1, MT, dir, a.periodic, 0};
-            walk_uniform<1, MT>(rd, wr, MT, sh, a.periodic, &ofl);
-            mine += (double)ofl;
-        }
-        __syncthreads();
-        if (threadIdx.x < nl) {
-            float inv = 1.0f;
-            if (Codec<P>::scaled) {
-                float m = 0.0f;
-#pragma unroll
-                for (int i = 0; i < MT; ++i) m = fmaxf(m, fabsf(wr.out[i]));
-                inv = inv_scale(m);
-                sout[gline + threadIdx.x] = m;
-            }
-            float* line = tile + threadIdx.x * LS;
-#pragma unroll
-            for (int i = 0; i < MT; ++i) line[dir > 0 ? i : MT - 1 - i] = wr.out[i] * inv;
-        }
-        __syncthreads();
-        T* dst = fout + gline * MT;
-        for (int e = threadIdx.x * 4; e < nl * MT; e += NT * 4) {
-            const int ln = e / MT;
-            const int off = e - ln * MT;
-            Pack<T, 4> q;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) q.v[u] = Codec<P>::enc(tile[ln * LS + off + u]);
-            *reinterpret_cast<Pack<T, 4>*>(dst + e) = q;
-        }
-        __syncthreads();
-    }
-    if (a.outflow != nullptr && !a.periodic) {
-        const double tot = block_sum(mine, red);
-        if (threadIdx.x == 0) a.outflow[cell] += tot * a.du3;
-    }
-}
-
-// Fallback for line lengths without a tiled kernel: one thread per contiguous
-// line straight from global memory (two passes for scaled storage).
-template <int P>
-__global__ void __launch_bounds__(256) k_vel_uz_generic(const typename Codec<P>::T* __restrict__ fin,
-                                                       const float* __restrict__ sin,
-                                                       typename Codec<P>::T* __restrict__ fout,
-                                                       float* __restrict__ sout, VelArgs a)
-{
-    __shared__ double red[4];
-    const long cell = blockIdx.x;
-    const int M = a.M;
-    const double s = (double)a.g[cell] * a.factor;
-    const LineShift sh = split_shift(s, M, a.periodic);
-    const int dir = sh.neg ? -1 : 1;
-    double mine = 0.0;
-    for (long l = threadIdx.x; l < a.nsub; l += blockDim.x) {
-        const long line = cell * a.nsub + l;
-        const float sc = Codec<P>::scaled ? sin[line] : 1.0f;
-        GlobalReader<P, 1, false> rd{fin + line * M, nullptr, 1, 0, M, dir, a.periodic, 0};
-        float ofl = 0.0f;
-        float inv = 1.0f;
-        if (Codec<P>::scaled) {
-            // pass 1: the output scale
-            struct ScaledReader {
-                GlobalReader<P, 1, false> g;
-                float sc;
-                __device__ void seek(int r) { g.seek(r); }
-                __device__ void next(float* x) { g.next(x); x[0] *= sc; }
-            };
-            ScaledReader srd{rd, sc};
-            MaxWriter mw{0.0f};
-            walk_uniform<1, 0>(srd, mw, M, sh, a.periodic, &ofl);
-            inv = inv_scale(mw.m);
-            sout[line] = mw.m;
-            ScaledReader srd2{rd, sc};
-            ContigWriter<P> cw{fout + line * M, M, dir, inv};
-            walk_uniform<1, 0>(srd2, cw, M, sh, a.periodic, &ofl);
-        } else {
-            ContigWriter<P> cw{fout + line * M, M, dir, 1.0f};
-            walk_uniform<1, 0>(rd, cw, M, sh, a.periodic, &ofl);
-        }
-        mine += (double)ofl;
-    }
-    if (a.outflow != nullptr && !a.periodic) {
-        const double tot = block_sum(mine, red);
-        if (threadIdx.x == 0) a.outflow[cell] += tot * a.du3;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Launchers
-// ---------------------------------------------------------------------------
-template <int P, int V>
-static hipError_t launch_position_v(const void* fin, const float* sin, void* fout, float* sout,
-                                    const PosArgs& a, hipStream_t st)
-{
-    using T = typename Codec<P>::T;
-    const long total = a.O * (a.I / V);
-    const unsigned blocks = (unsigned)((total + 255) / 256);
-    if (total == 0) return hipSuccess;
-#define VL_POS(MTV) \
-    hipLaunchKernelGGL((k_position<P, V, MTV>), dim3(blocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a)
-    switch (a.M) {
-        case 16: VL_POS(16); break;
-        case 32: VL_POS(32); break;
-        case 64: VL_POS(64); break;
-        default: VL_POS(0); break;
-    }
-#undef VL_POS
-    return hipGetLastError();
-}
-
-template <int P>
-static hipError_t launch_position_p(const void* fin, const float* sin, void* fout, float* sout,
-                                    const PosArgs& a, hipStream_t st)
-{
-    switch (a.V) {
-        case 4: return launch_position_v<P, 4>(fin, sin, fout, sout, a, st);
-        case 2: return launch_position_v<P, 2>(fin, sin, fout, sout, a, st);
-        default: return launch_position_v<P, 1>(fin, sin, fout, sout, a, st);
-    }
-}
+#define VL_DECL(NAME, ARGS)                                                                      \
+    hipError_t NAME##_f32(const void*, const float*, void*, float*, const ARGS&, hipStream_t);  \
+    hipError_t NAME##_f16(const void*, const float*, void*, float*, const ARGS&, hipStream_t);  \
+    hipError_t NAME##_bf16(const void*, const float*, void*, float*, const ARGS&, hipStream_t);
+VL_DECL(launch_position, PosArgs)
+VL_DECL(launch_vel_strided, VelArgs)
+VL_DECL(launch_vel_uz, VelArgs)
+#undef VL_DECL
 
 hipError_t launch_position(int prec, const void* fin, const float* sin, void* fout, float* sout,
                            const PosArgs& a, hipStream_t st)
 {
     switch (prec) {
-        case PREC_F16: return launch_position_p<PREC_F16>(fin, sin, fout, sout, a, st);
-        case PREC_BF16: return launch_position_p<PREC_BF16>(fin, sin, fout, sout, a, st);
-        default: return launch_position_p<PREC_F32>(fin, sin, fout, sout, a, st);
-    }
-}
-
-template <int P, int V>
-static hipError_t launch_vel_strided_v(const void* fin, const float* sin, void* fout, float* sout,
-                                       const VelArgs& a, hipStream_t st)
-{
-    using T = typename Codec<P>::T;
-    if (a.cells == 0) return hipSuccess;
-    const long lpc = (long)a.nsub * (a.I / V);
-    long bs = ((lpc + 63) / 64) * 64;
-    if (bs > 256) bs = 256;
-#define VL_VEL(MTV) \
-    hipLaunchKernelGGL((k_vel_strided<P, V, MTV>), dim3((unsigned)a.cells), dim3((unsigned)bs), 0, st, (const T*)fin, sin, (T*)fout, sout, a)
-    switch (a.M) {
-        case 16: VL_VEL(16); break;
-        case 32: VL_VEL(32); break;
-        case 64: VL_VEL(64); break;
-        default: VL_VEL(0); break;
-    }
-#undef VL_VEL
-    return hipGetLastError();
-}
-
-template <int P>
-static hipError_t launch_vel_strided_p(const void* fin, const float* sin, void* fout, float* sout,
-                                       const VelArgs& a, hipStream_t st)
-{
-    switch (a.V) {
-        case 4: return launch_vel_strided_v<P, 4>(fin, sin, fout, sout, a, st);
-        case 2: return launch_vel_strided_v<P, 2>(fin, sin, fout, sout, a, st);
-        default: return launch_vel_strided_v<P, 1>(fin, sin, fout, sout, a, st);
+        case PREC_F16: return launch_position_f16(fin, sin, fout, sout, a, st);
+        case PREC_BF16: return launch_position_bf16(fin, sin, fout, sout, a, st);
+        default: return launch_position_f32(fin, sin, fout, sout, a, st);
     }
 }
 
@@ -311,45 +30,19 @@ hipError_t launch_vel_strided(int prec, const void* fin, const float* sin, void*
                               const VelArgs& a, hipStream_t st)
 {
     switch (prec) {
-        case PREC_F16: return launch_vel_strided_p<PREC_F16>(fin, sin, fout, sout, a, st);
-        case PREC_BF16: return launch_vel_strided_p<PREC_BF16>(fin, sin, fout, sout, a, st);
-        default: return launch_vel_strided_p<PREC_F32>(fin, sin, fout, sout, a, st);
+        case PREC_F16: return launch_vel_strided_f16(fin, sin, fout, sout, a, st);
+        case PREC_BF16: return launch_vel_strided_bf16(fin, sin, fout, sout, a, st);
+        default: return launch_vel_strided_f32(fin, sin, fout, sout, a, st);
     }
-}
-
-template <int P>
-static hipError_t launch_vel_uz_p(const void* fin, const float* sin, void* fout, float* sout,
-                                  const VelArgs& a, hipStream_t st)
-{
-    using T = typename Codec<P>::T;
-    if (a.cells == 0) return hipSuccess;
-    const dim3 grid((unsigned)a.cells);
-    switch (a.M) {
-        case 16:
-            hipLaunchKernelGGL((k_vel_uz<P, 16, 256>), grid, dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a);
-            break;
-        case 32:
-            hipLaunchKernelGGL((k_vel_uz<P, 32, 256>), grid, dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a);
-            break;
-        case 64:
-            hipLaunchKernelGGL((k_vel_uz<P, 64, 128>), grid, dim3(128), 0, st, (const T*)fin, sin, (T*)fout, sout, a);
-            break;
-        default: {
-            long bs = ((a.nsub + 63) / 64) * 64;
-            if (bs > 256) bs = 256;
-            hipLaunchKernelGGL((k_vel_uz_generic<P>), grid, dim3((unsigned)bs), 0, st, (const T*)fin, sin, (T*)fout, sout, a);
-        }
-    }
-    return hipGetLastError();
 }
 
 hipError_t launch_vel_uz(int prec, const void* fin, const float* sin, void* fout, float* sout,
                          const VelArgs& a, hipStream_t st)
 {
     switch (prec) {
-        case PREC_F16: return launch_vel_uz_p<PREC_F16>(fin, sin, fout, sout, a, st);
-        case PREC_BF16: return launch_vel_uz_p<PREC_BF16>(fin, sin, fout, sout, a, st);
-        default: return launch_vel_uz_p<PREC_F32>(fin, sin, fout, sout, a, st);
+        case PREC_F16: return launch_vel_uz_f16(fin, sin, fout, sout, a, st);
+        case PREC_BF16: return launch_vel_uz_bf16(fin, sin, fout, sout, a, st);
+        default: return launch_vel_uz_f32(fin, sin, fout, sout, a, st);
     }
 }
 
