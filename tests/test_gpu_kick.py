@@ -49,3 +49,29 @@ def test_kick_equals_three_sweeps(prec, shape, vbc, cfl):
         assert torch.equal(k.scale, c.scale)
     # per-line partial sums are FP32 and grouped differently (4 lines per thread vs 1)
     np.testing.assert_allclose(o2.cpu().numpy(), o1.cpu().numpy(), rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("prec", [V.F32, V.F16])
+def test_step_equals_its_five_launches(prec):
+    """vlasov_step is kick(g_n), z, y, x, kick(g_np1); bench.py times those five
+    launches one by one, so both must give the same bits."""
+    print("case: step vs five launches", V.PREC_NAME[prec], flush=True)
+    n, nu = (6, 5, 4), (16, 16, 16)
+    hg = V.make_grid(n, nu, (1.0, 1.3, 0.8), (1.0, 0.9, 1.1))
+    rng = np.random.default_rng(11)
+    f = torch.from_numpy(rng.uniform(0, 1, V.grid_shape(hg)).astype(np.float32) ** 2).cuda()
+    st = V.encode(hg, prec, f)
+    dt = 0.21
+    gs = [torch.from_numpy(rng.uniform(-3, 3, (3,) + n).astype(np.float32)).cuda() for _ in range(2)]
+    o1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    o2 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ref = V.step(st, gs[0], gs[1], dt, outflow=o1)
+    a = V.kick(st, gs[0], 0.5 * dt, outflow=o2)
+    for ax in ("z", "y", "x"):
+        a = V.advect(ax, a, dt)
+    b = V.kick(a, gs[1], 0.5 * dt, outflow=o2)
+    torch.cuda.synchronize()
+    assert torch.equal(b.f, ref.f)
+    if prec != V.F32:
+        assert torch.equal(b.scale, ref.scale)
+    assert torch.equal(o1, o2)
