@@ -140,11 +140,15 @@ int vlasov_advect_uz(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc,
 /*
  * Velocity kick: D_uz D_uy D_ux over dt with one field g, i.e. the three
  * velocity sweeps of one half step of Eq. (5) (with dt the half step).
- * The result is bitwise that of vlasov_advect_ux, _uy, _uz in sequence.
  * Velocity blocks of 16^3 or 32^3 cells are swept inside LDS (one HBM read
  * and one write of f instead of three); other shapes run the three sweeps
  * and then need `work` (vlasov_step_workspace_bytes, else VLASOV_ERR_WORKSPACE);
- * work may be NULL for the fused shapes.
+ * work may be NULL for the fused shapes.  With FP32 storage the result is
+ * bitwise that of vlasov_advect_ux, _uy, _uz in sequence.  With FP16/BF16
+ * storage the fused shapes keep the values between the three sweeps in FP32
+ * and round only the result, so they differ from the three single sweeps by
+ * those sweeps' two intermediate roundings (about one code unit of the line
+ * scale); the outflow tally differs by the same relative amount.
  */
 int vlasov_kick(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, const void* f_in,
                 const float* scale_in, void* f_out, float* scale_out, const float* g, double dt,

@@ -183,7 +183,7 @@ size_t lds_limit()
 // block fits, otherwise three single sweeps through `mid` buffers.
 int run_kick(const vlasov_grid* g, const Dims& d, int prec, int vbc, const void* fin,
              const float* sin, void* fout, float* sout, void* midf, float* mids,
-             const float* field, double dt, double* outflow, hipStream_t st)
+             const float* field, double dt, double* outflow, KickShift* shifts, hipStream_t st)
 {
     if (!isfinite(dt)) return VLASOV_ERR_NONFINITE;
     int nu[3] = {(int)d.nu[0], (int)d.nu[1], (int)d.nu[2]};
@@ -201,7 +201,7 @@ int run_kick(const vlasov_grid* g, const Dims& d, int prec, int vbc, const void*
         a.du3 = (2.0 * g->umax[0] / g->nu[0]) * (2.0 * g->umax[1] / g->nu[1]) *
                 (2.0 * g->umax[2] / g->nu[2]);
         a.cells = d.cells;
-        return from_hip(launch_kick(prec, fin, sin, fout, sout, a, st));
+        return from_hip(launch_kick(prec, fin, sin, fout, sout, a, shifts, st));
     }
     if (midf == nullptr) return VLASOV_ERR_WORKSPACE;
     int rc = run_velocity(g, d, 0, prec, vbc, fin, sin, fout, sout, field, dt, outflow, st);
@@ -311,13 +311,19 @@ int vlasov_advect_uz(const vlasov_grid* g, vlasov_prec p, vlasov_vbc vbc, const 
     return advect_velocity(g, 2, p, vbc, fin, sin, fout, sout, field, dt, outflow, stream);
 }
 
+// Step workspace: one copy of f, its scales, then the kick's shift table.
+static size_t shift_table_offset(const Dims& d, int prec)
+{
+    size_t b = align_up((size_t)d.total * elem_bytes(prec));
+    if (prec != VLASOV_F32) b += align_up((size_t)(d.total / d.nu[2]) * sizeof(float));
+    return b;
+}
+
 size_t vlasov_step_workspace_bytes(const vlasov_grid* grid, vlasov_prec prec)
 {
     Dims d;
     if (!dims_of(grid, d) || !prec_ok(prec)) return 0;
-    size_t b = align_up((size_t)d.total * elem_bytes(prec));
-    if (prec != VLASOV_F32) b += align_up((size_t)(d.total / d.nu[2]) * sizeof(float));
-    return b;
+    return shift_table_offset(d, prec) + align_up((size_t)(3 * d.cells) * sizeof(KickShift));
 }
 
 int vlasov_step(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
@@ -348,18 +354,19 @@ int vlasov_step(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const vo
         overlap(fout, fb, g_np1, 3 * d.cells * sizeof(float)))
         return VLASOV_ERR_ALIAS;
     hipStream_t st = (hipStream_t)stream;
+    KickShift* tab = (KickShift*)((char*)work + shift_table_offset(d, prec));
     const double h = 0.5 * dt;
     const double dta = dt * a2inv;
     // Eq. (5) right to left: kick(g_n) -> z -> y -> x -> kick(g_np1).
     // Buffers: in -> out (kick) -> work (z) -> out (y) -> work (x) -> out (kick);
     // a kick that cannot run fused uses the other buffer as its middle stage.
-    if ((rc = run_kick(g, d, prec, vbc, fin, sin, fout, sout, wf, ws, g_n, h, outflow, st)))
+    if ((rc = run_kick(g, d, prec, vbc, fin, sin, fout, sout, wf, ws, g_n, h, outflow, tab, st)))
         return rc;
     if ((rc = run_position(g, d, 2, prec, fout, sout, wf, ws, dta, st))) return rc;
     if ((rc = run_position(g, d, 1, prec, wf, ws, fout, sout, dta, st))) return rc;
     if ((rc = run_position(g, d, 0, prec, fout, sout, wf, ws, dta, st))) return rc;
     if ((rc = run_kick(g, d, prec, vbc, wf, ws, fout, sout, nullptr, nullptr, g_np1, h, outflow,
-                       st)) == VLASOV_ERR_WORKSPACE) {
+                       tab, st)) == VLASOV_ERR_WORKSPACE) {
         // unfused last kick: x result is in work; go work -> out -> work -> out
         if ((rc = run_velocity(g, d, 0, prec, vbc, wf, ws, fout, sout, g_np1, h, outflow, st)))
             return rc;
@@ -387,18 +394,25 @@ int vlasov_kick(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const vo
         return VLASOV_ERR_ALIAS;
     void* wf = nullptr;
     float* ws = nullptr;
+    KickShift* tab = nullptr;
     int nu[3] = {(int)d.nu[0], (int)d.nu[1], (int)d.nu[2]};
-    if (!kick_supported(nu, lds_limit())) {
-        const size_t need = vlasov_step_workspace_bytes(g, prec);
-        if (work == nullptr || work_bytes < need) return VLASOV_ERR_WORKSPACE;
+    const bool fused = kick_supported(nu, lds_limit());
+    const size_t need = vlasov_step_workspace_bytes(g, prec);
+    // fused shapes run without a workspace (then every work-group splits its
+    // own shifts); with one they precompute the shift table into it
+    if (!fused && (work == nullptr || work_bytes < need)) return VLASOV_ERR_WORKSPACE;
+    if (work != nullptr && work_bytes >= need) {
         const size_t sb = prec == VLASOV_F32 ? 0 : (size_t)(d.total / d.nu[2]) * sizeof(float);
         if (overlap(work, need, fin, fb) || overlap(work, need, fout, fb) ||
-            overlap(work, need, sin, sb) || overlap(work, need, sout, sb))
+            overlap(work, need, sin, sb) || overlap(work, need, sout, sb) ||
+            overlap(work, need, field, 3 * d.cells * sizeof(float)) ||
+            (outflow != nullptr && overlap(work, need, outflow, d.cells * sizeof(double))))
             return VLASOV_ERR_ALIAS;
         wf = work;
         ws = prec == VLASOV_F32 ? nullptr : (float*)((char*)work + align_up(fb));
+        tab = (KickShift*)((char*)work + shift_table_offset(d, prec));
     }
-    return run_kick(g, d, prec, vbc, fin, sin, fout, sout, wf, ws, field, dt, outflow,
+    return run_kick(g, d, prec, vbc, fin, sin, fout, sout, wf, ws, field, dt, outflow, tab,
                     (hipStream_t)stream);
 }
 

@@ -6,10 +6,12 @@
 // section 5.1.3), so a work-group can hold the whole block (32^3 FP32 values
 // = 128 KiB of MI355X's 160 KiB LDS), run ux, uy and uz on it, and touch HBM
 // once for reading and once for writing instead of three times each.  Each
-// sweep performs the same FP32 operations as the single-sweep kernels, and
-// with FP16/BF16 storage the intermediate results are rounded exactly as if
-// they had been stored, so the result is bitwise the one of the three
-// separate sweeps.
+// sweep performs the same FP32 operations as the single-sweep kernels, so
+// with FP32 storage the result is bitwise the one of the three separate
+// sweeps.  With FP16/BF16 storage only the result is stored: the values
+// between the three sweeps stay FP32 in LDS (the storage format is what
+// lives in HBM), which saves the two intermediate roundings the separate
+// sweeps make -- the fused result is the more accurate one.
 //
 // The work-groups are persistent (as many as fit on the chip, each walking
 // cells blockIdx.x, blockIdx.x + gridDim.x, ...).  While one block is swept
@@ -30,23 +32,6 @@
 #include "sl_mpp5.hpp"
 
 namespace vlasov {
-
-// Round the uz-line held by this thread in LDS as storage would: its scale
-// is the largest |value|, each value becomes code * scale.
-template <int P, int NZ>
-__device__ __forceinline__ void storage_round_line(float* line)
-{
-    float x[NZ];
-    float m = 0.0f;
-#pragma unroll
-    for (int i = 0; i < NZ; ++i) {
-        x[i] = line[i];
-        m = fmaxf(m, fabsf(x[i]));
-    }
-    const float inv = inv_scale(m);
-#pragma unroll
-    for (int i = 0; i < NZ; ++i) line[i] = Codec<P>::dec(quantize<P>(x[i], inv)) * m;
-}
 
 // One thread's share of a velocity block in flight from HBM: NS slots of 4
 // consecutive values of one uz-line, with that line's scale.
@@ -181,13 +166,24 @@ __device__ __forceinline__ float kick_axis_dir(float* line, const LineShift& sh,
 
 template <int P, int NU, bool PER, int AXIS>
 __device__ __forceinline__ float kick_axis(float* lds, float* sout_line, float* lmax_line,
-                                           const KickArgs& a, float g, int t)
+                                           const KickArgs& a, const KickShift* __restrict__ tab,
+                                           int cell, float g, int t)
 {
     constexpr int LS = NU + 1;
     const int base = AXIS == 0 ? (t / NU) * LS + (t % NU)
                    : AXIS == 1 ? (t / NU) * NU * LS + (t % NU)
                                : t * LS;
-    const LineShift sh = split_shift((double)g * a.factor[AXIS], NU, PER);
+    LineShift sh;
+    if (tab != nullptr) {
+        // scalar loads of the precomputed split (uniform over the work-group)
+        const KickShift e = tab[(long)cell * 3 + AXIS];
+        sh.N = e.N;
+        sh.neg = e.neg != 0;
+        sh.mu = e.mu;
+        sh.v0 = e.v0; sh.v1 = e.v1; sh.v2 = e.v2; sh.v3 = e.v3;
+    } else {
+        sh = split_shift((double)g * a.factor[AXIS], NU, PER);
+    }
     const int N = uniform_sgpr(sh.N);
     if (uniform_sgpr(sh.neg ? 1 : 0))
         return kick_axis_dir<P, NU, PER, AXIS, true>(lds + base, sh, N, sout_line, lmax_line);
@@ -224,7 +220,8 @@ template <int P, int NU, bool PER>
 __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __restrict__ fin,
                                                 const float* __restrict__ sin,
                                                 typename Codec<P>::T* __restrict__ fout,
-                                                float* __restrict__ sout, KickArgs a)
+                                                float* __restrict__ sout, KickArgs a,
+                                                const KickShift* __restrict__ tab)
 {
     using T = typename Codec<P>::T;
     using Slots = BlockSlots<P, NU>;
@@ -251,20 +248,12 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
 
     for (;;) {
         float o[3];
-        o[0] = kick_axis<P, NU, PER, 0>(lds, nullptr, nullptr, a, g[0], t);
+        o[0] = kick_axis<P, NU, PER, 0>(lds, nullptr, nullptr, a, tab, cell, g[0], t);
         __syncthreads();
-        if (Codec<P>::scaled) {
-            storage_round_line<P, NU>(lds + t * (NU + 1));
-            __syncthreads();
-        }
-        o[1] = kick_axis<P, NU, PER, 1>(lds, nullptr, nullptr, a, g[1], t);
+        o[1] = kick_axis<P, NU, PER, 1>(lds, nullptr, nullptr, a, tab, cell, g[1], t);
         __syncthreads();
-        if (Codec<P>::scaled) {
-            storage_round_line<P, NU>(lds + t * (NU + 1));
-            __syncthreads();
-        }
         o[2] = kick_axis<P, NU, PER, 2>(lds, Codec<P>::scaled ? sout + (long)cell * NL + t : nullptr,
-                                        lmax + t, a, g[2], t);
+                                        lmax + t, a, tab, cell, g[2], t);
         __syncthreads();
 
         if (a.outflow != nullptr && !PER) {
@@ -304,9 +293,27 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
     }
 }
 
+// The split of every (cell, axis) shift of a kick, one thread each.
+__global__ void __launch_bounds__(256) k_kick_shifts(KickArgs a, KickShift* __restrict__ tab)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * a.cells) return;
+    const long cell = i / 3;
+    const int axis = (int)(i - cell * 3);
+    const LineShift sh = split_shift((double)a.g[(long)axis * a.cells + cell] * a.factor[axis],
+                                     a.nu[axis], a.periodic);
+    KickShift e;
+    e.N = sh.N;
+    e.neg = sh.neg ? 1 : 0;
+    e.mu = sh.mu;
+    e.v0 = sh.v0; e.v1 = sh.v1; e.v2 = sh.v2; e.v3 = sh.v3;
+    e.pad = 0.0f;
+    tab[i] = e;
+}
+
 template <int P, int N, bool PER>
 static hipError_t launch_kick_t(const void* fin, const float* sin, void* fout, float* sout,
-                                const KickArgs& a, hipStream_t st)
+                                const KickArgs& a, const KickShift* tab, hipStream_t st)
 {
     using T = typename Codec<P>::T;
     const size_t lds = (size_t)N * N * (N + 1) * sizeof(float);
@@ -325,20 +332,20 @@ static hipError_t launch_kick_t(const void* fin, const float* sin, void* fout, f
     long grid = (long)cus * (per_cu > 0 ? per_cu : 1);
     if (grid > a.cells) grid = a.cells;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(N * N), lds, st, (const T*)fin, sin,
-                       (T*)fout, sout, a);
+                       (T*)fout, sout, a, tab);
     return hipGetLastError();
 }
 
 template <int P>
 static hipError_t launch_kick_p(const void* fin, const float* sin, void* fout, float* sout,
-                                const KickArgs& a, hipStream_t st)
+                                const KickArgs& a, const KickShift* tab, hipStream_t st)
 {
     if (a.nu[0] == 32) {
-        return a.periodic ? launch_kick_t<P, 32, true>(fin, sin, fout, sout, a, st)
-                          : launch_kick_t<P, 32, false>(fin, sin, fout, sout, a, st);
+        return a.periodic ? launch_kick_t<P, 32, true>(fin, sin, fout, sout, a, tab, st)
+                          : launch_kick_t<P, 32, false>(fin, sin, fout, sout, a, tab, st);
     }
-    return a.periodic ? launch_kick_t<P, 16, true>(fin, sin, fout, sout, a, st)
-                      : launch_kick_t<P, 16, false>(fin, sin, fout, sout, a, st);
+    return a.periodic ? launch_kick_t<P, 16, true>(fin, sin, fout, sout, a, tab, st)
+                      : launch_kick_t<P, 16, false>(fin, sin, fout, sout, a, tab, st);
 }
 
 bool kick_supported(const int nu[3], size_t lds_limit)
@@ -350,14 +357,21 @@ bool kick_supported(const int nu[3], size_t lds_limit)
 }
 
 hipError_t launch_kick(int prec, const void* fin, const float* sin, void* fout, float* sout,
-                       const KickArgs& a, hipStream_t st)
+                       const KickArgs& a, KickShift* shifts, hipStream_t st)
 {
     if (a.cells == 0) return hipSuccess;
     if (a.cells > 0x7fffffffL) return hipErrorInvalidValue;   // cell indices are int
+    if (shifts != nullptr) {
+        const long n = 3 * a.cells;
+        hipLaunchKernelGGL(k_kick_shifts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a,
+                           shifts);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     switch (prec) {
-        case PREC_F16: return launch_kick_p<PREC_F16>(fin, sin, fout, sout, a, st);
-        case PREC_BF16: return launch_kick_p<PREC_BF16>(fin, sin, fout, sout, a, st);
-        default: return launch_kick_p<PREC_F32>(fin, sin, fout, sout, a, st);
+        case PREC_F16: return launch_kick_p<PREC_F16>(fin, sin, fout, sout, a, shifts, st);
+        case PREC_BF16: return launch_kick_p<PREC_BF16>(fin, sin, fout, sout, a, shifts, st);
+        default: return launch_kick_p<PREC_F32>(fin, sin, fout, sout, a, shifts, st);
     }
 }
 

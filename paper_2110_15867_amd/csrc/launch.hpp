@@ -45,6 +45,17 @@ hipError_t launch_vel_strided(int prec, const void* fin, const float* sin, void*
 hipError_t launch_vel_uz(int prec, const void* fin, const float* sin, void* fout, float* sout,
                          const VelArgs& a, hipStream_t st);
 
+// Split shift of one velocity line (uniform over a spatial cell's block):
+// integer part, direction and the fractional part's interface weights in
+// difference form; precomputed per cell and axis for the fused kick.
+struct KickShift {
+    int N;
+    int neg;
+    float mu;
+    float v0, v1, v2, v3;
+    float pad;
+};
+
 // Fused kick: the three velocity sweeps of one half step (Eq. 5) in LDS.
 struct KickArgs {
     const float* g;  // field [3][cells]
@@ -56,8 +67,10 @@ struct KickArgs {
     int nu[3];
 };
 bool kick_supported(const int nu[3], size_t lds_limit);
+// shifts: [cells][3] table written by the kick's own pre-pass on the same
+// stream when given, else each work-group splits its shifts itself
 hipError_t launch_kick(int prec, const void* fin, const float* sin, void* fout, float* sout,
-                       const KickArgs& a, hipStream_t st);
+                       const KickArgs& a, KickShift* shifts, hipStream_t st);
 
 struct MomArgs {
     long cells;
