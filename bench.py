@@ -9,8 +9,10 @@ before the timed region.
 
 Prints ONE JSON line: cell-updates/s per full step, the algorithmic HBM rate,
 a roofline entry for the slowest launch (HIP events on the launch stream: the
-fused kick, bound by vector ALU issue, or a drift sweep, bound by HBM) and
-the FP64 CPU oracle timed on a bounded sample on the host cores.
+fused kick, bound by vector ALU issue, or a drift sweep, bound by HBM), the
+same workload with FP16 storage (speedup against FP32; skipped with
+--no-fp16 or when --prec is not f32) and the FP64 CPU oracle timed on a
+bounded sample on the host cores.
 """
 from __future__ import annotations
 
@@ -106,50 +108,8 @@ def cpu_baseline(seconds: float = 12.0):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", default="f32", choices=["f32", "f16", "bf16"])
-    ap.add_argument("--workload", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the sweeps shard along space across GPUs "
-              "(design only, not built); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    from paper_2110_15867_amd import inputs
-    from paper_2110_15867_amd import vlasov as V
-
-    prec = {"f32": V.F32, "f16": V.F16, "bf16": V.BF16}[args.prec]
-    w = inputs.workload(args.workload)
-    grid = V.make_grid(w.n, w.nu, w.L, w.umax)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    stream = torch.cuda.current_stream()
-    K, W = args.steps, args.warmup
-    _log(f"bench: {w.name}, {w.cells:.3e} cells, prec {args.prec}, warmup {W}, steps {K}")
-
-    # ---- HBM copy probe: the practical ceiling of a streaming kernel ----
-    probe_bytes = 8 << 30
-    a_buf = torch.empty(probe_bytes, dtype=torch.uint8, device=dev)
-    b_buf = torch.empty(probe_bytes, dtype=torch.uint8, device=dev)
-    a_buf.fill_(1)
-    V.vlasov_stream_copy(a_buf, b_buf, probe_bytes, stream)
-    pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    pe[0].record(stream)
-    for _ in range(5):
-        V.vlasov_stream_copy(a_buf, b_buf, probe_bytes, stream)
-    pe[1].record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * probe_bytes / (pe[0].elapsed_time(pe[1]) * 1e-3) / 1e9
-    del a_buf, b_buf
-    _log(f"bench: copy probe {copy_gbs:.0f} GB/s (read + write)")
-
+def timed_run(V, torch, inputs, w, grid, prec, K, W, dev, stream):
+    """K timed steps of one storage form; inputs resident in HBM first."""
     # ---- inputs resident in HBM ----
     f0 = inputs.initial_f32_device(w, dev)
     state = V.encode(grid, prec, f0)
@@ -217,8 +177,59 @@ def main():
     for k in range(K):
         for i, nm in enumerate(names):
             per[nm].append(evs[k][i].elapsed_time(evs[k][i + 1]))
-    state, out = bufA, bufB
-    del wf, bufC
+    del wf, bufA, bufB, bufC, state, out, work, fields, outflow
+    torch.cuda.empty_cache()
+    return {"total_ms": total_ms, "step_ms": step_ms, "per": per, "t_wall": t_wall}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--workload", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true",
+                    help="skip the FP16-storage companion run of an FP32 bench")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the sweeps shard along space across GPUs "
+              "(design only, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2110_15867_amd import inputs
+    from paper_2110_15867_amd import vlasov as V
+
+    prec = {"f32": V.F32, "f16": V.F16, "bf16": V.BF16}[args.prec]
+    w = inputs.workload(args.workload)
+    grid = V.make_grid(w.n, w.nu, w.L, w.umax)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    K, W = args.steps, args.warmup
+    _log(f"bench: {w.name}, {w.cells:.3e} cells, prec {args.prec}, warmup {W}, steps {K}")
+
+    # ---- HBM copy probe: the practical ceiling of a streaming kernel ----
+    probe_bytes = 8 << 30
+    a_buf = torch.empty(probe_bytes, dtype=torch.uint8, device=dev)
+    b_buf = torch.empty(probe_bytes, dtype=torch.uint8, device=dev)
+    a_buf.fill_(1)
+    V.vlasov_stream_copy(a_buf, b_buf, probe_bytes, stream)
+    pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    pe[0].record(stream)
+    for _ in range(5):
+        V.vlasov_stream_copy(a_buf, b_buf, probe_bytes, stream)
+    pe[1].record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * probe_bytes / (pe[0].elapsed_time(pe[1]) * 1e-3) / 1e9
+    del a_buf, b_buf
+    _log(f"bench: copy probe {copy_gbs:.0f} GB/s (read + write)")
+
+    r = timed_run(V, torch, inputs, w, grid, prec, K, W, dev, stream)
+    total_ms, step_ms, per = r["total_ms"], r["step_ms"], r["per"]
     avg = {k: statistics.mean(v) for k, v in per.items()}
     dominant = max(avg, key=avg.get)
     bpc = algorithmic_bytes_per_cell(prec, w.nu[2])
@@ -279,12 +290,28 @@ def main():
                    "dt": w.dt, "sweeps_per_step": 9, "launches_per_step": 5,
                    "storage": args.prec},
         "hbm_tbps_algorithmic": step_bytes / (total_ms / K * 1e-3) / 1e12,
+        # the nine sweeps of Eq. (5) counted separately, as if unfused
+        "hbm_tbps_nine_sweep_equivalent": 9 * launch_bytes / (total_ms / K * 1e-3) / 1e12,
         "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
         "copy_probe_gbs": copy_gbs,
         "roofline": roofline,
     }
-    del state, out, work, fields
-    torch.cuda.empty_cache()
+    if args.prec == "f32" and not args.no_fp16:
+        # the FP16-storage form of the same workload, for the FP16 vs FP32
+        # comparison (its error against the FP64 oracle is a GPU test)
+        r16 = timed_run(V, torch, inputs, w, grid, V.F16, K, W, dev, stream)
+        avg16 = {k: statistics.mean(v) for k, v in r16["per"].items()}
+        ms16 = r16["total_ms"] / K
+        bytes16 = 5 * algorithmic_bytes_per_cell(V.F16, w.nu[2]) * w.cells
+        res["fp16_storage"] = {
+            "value": w.cells * K / (r16["total_ms"] * 1e-3),
+            "ms_per_step": ms16,
+            "median_ms_per_step": statistics.median(r16["step_ms"]),
+            "speedup_vs_f32": (total_ms / K) / ms16,
+            "kernel_ms": {k: round(v, 4) for k, v in avg16.items()},
+            "hbm_tbps_algorithmic": bytes16 / (ms16 * 1e-3) / 1e12,
+        }
+        _log("bench: fp16 per-kernel ms " + json.dumps({k: round(v, 3) for k, v in avg16.items()}))
     if not args.no_cpu_baseline:
         _log("bench: timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline()

@@ -171,9 +171,15 @@ struct URowReader {
     }
     __device__ void next(float* x)
     {
-        const T* row = base + (long)phys * stride;
-        const float sc = Codec<P>::scaled ? (sbase + (long)phys * sstride)[soff] : 1.0f;
-        load_row<P, V>(row + loff, sc, x);
+        // scalar row address + this lane's 32-bit byte offset: the form the
+        // global loads take with an SGPR base and a VGPR offset
+        const char* row = reinterpret_cast<const char*>(base + (long)phys * stride);
+        float sc = 1.0f;
+        if (Codec<P>::scaled) {
+            const char* srow = reinterpret_cast<const char*>(sbase + (long)phys * sstride);
+            sc = *reinterpret_cast<const float*>(srow + (unsigned)(soff * sizeof(float)));
+        }
+        load_row<P, V>(reinterpret_cast<const T*>(row + (unsigned)(loff * sizeof(T))), sc, x);
         phys += dir;
         if (phys == M) phys = 0;
         else if (phys < 0) phys = M - 1;
@@ -196,17 +202,21 @@ struct URowWriter {
     __device__ void put(int i, const float* x)
     {
         const long p = dir > 0 ? i : M - 1 - i;
-        T* row = base + p * stride;
+        char* row = reinterpret_cast<char*>(base + p * stride);
+        T* dst = reinterpret_cast<T*>(row + (unsigned)(loff * sizeof(T)));
         if (Codec<P>::scaled) {
             float m = 0.0f;
 #pragma unroll
             for (int v = 0; v < V; ++v) m = fmaxf(m, fabsf(x[v]));
             m = GC > 0 ? group_max_nonneg<GC>(m) : group_max(m, G);
             const float inv = inv_scale(m);
-            store_row<P, V>(row + loff, x, inv);
-            if ((threadIdx.x & (G - 1)) == 0) (sbase + p * sstride)[soff] = m;
+            store_row<P, V>(dst, x, inv);
+            if ((threadIdx.x & (G - 1)) == 0) {
+                char* srow = reinterpret_cast<char*>(sbase + p * sstride);
+                *reinterpret_cast<float*>(srow + (unsigned)(soff * sizeof(float))) = m;
+            }
         } else {
-            store_row<P, V>(row + loff, x, 1.0f);
+            store_row<P, V>(dst, x, 1.0f);
         }
     }
 };

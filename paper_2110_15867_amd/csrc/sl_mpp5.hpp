@@ -50,6 +50,13 @@ __device__ __forceinline__ int uniform_sgpr(int v)
     return __builtin_amdgcn_readfirstlane(v);
 }
 
+__device__ __forceinline__ long uniform_long(long v)
+{
+    const unsigned lo = (unsigned)uniform_sgpr((int)(unsigned)v);
+    const unsigned hi = (unsigned)uniform_sgpr((int)(unsigned)((unsigned long)v >> 32));
+    return (long)(((unsigned long)hi << 32) | lo);
+}
+
 __device__ __forceinline__ float uniform_f32(float v)
 {
     return __builtin_bit_cast(float, uniform_sgpr(__builtin_bit_cast(int, v)));

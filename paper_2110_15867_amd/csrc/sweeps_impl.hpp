@@ -71,13 +71,16 @@ __global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __
     const int Ns = sh.neg ? -sh.N : sh.N;
     const int key = one_dir ? sh.N : Ns;
     const int key0 = __builtin_amdgcn_readfirstlane(key);
-    const bool urows = act == ~0ull && __ballot(key == key0) == act && (a.I / V) % 64 == 0;
+    const bool full = act == ~0ull && (a.I / V) % 64 == 0;
+    const bool urows = full && __ballot(key == key0) == act;
     if (urows) {
         const long t0 = t - (threadIdx.x & 63);          // lane 0 of this wave
         const long o0 = t0 / IV;
         const long k0 = (t0 - o0 * IV) * V;
-        const long ub = o0 * (long)M * a.I + k0;          // uniform element base
-        const long usb = o0 * (long)M * sI + k0 / a.nuz;
+        // (wave-uniform, kept in scalar registers: the row addresses are then
+        // SGPR bases and each access adds only the lane's 32-bit offset)
+        const long ub = uniform_long(o0 * (long)M * a.I + k0);
+        const long usb = uniform_long(o0 * (long)M * sI + k0 / a.nuz);
         const unsigned loff = (unsigned)(k - k0);
         const unsigned soff = (unsigned)(k / a.nuz - k0 / a.nuz);
         LineShift shu = sh;

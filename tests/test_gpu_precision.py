@@ -2,9 +2,13 @@
 
 The FP64 oracle has no storage rounding, so the comparison states an error:
 per sweep, each decoded output lies within the code's half-ulp of its line
-scale (plus the FP32 bar); after ten Strang steps on the seeded tiny workload
-the density's relative L2 error stays within 2e-3.
+scale (plus the FP32 bar); after ten Strang steps the density's relative L2
+error stays within 2e-3, on the seeded tiny workload and at the precision
+form's stated size, 32^3 x 32^3 (reference density from the FP64 oracle,
+tests/golden/make_density_32x32.py).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -103,3 +107,44 @@ def test_scaled_storage_rejects_unsupported_lines():
     with pytest.raises(V.VlasovError) as e:
         V.vlasov_advect_x(hg, V.F16, f, s, torch.empty_like(f), torch.empty_like(s), 0.1)
     assert e.value.code == -2
+
+
+GOLDEN_32 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                         "density_32x32_10steps.npz")
+
+
+@pytest.fixture(scope="module")
+def ic_32x32():
+    w = inputs.workload(2)
+    return w, torch.from_numpy(inputs.initial_f32(w))
+
+
+@pytest.mark.parametrize("prec", [V.F32, V.F16, V.BF16])
+def test_density_error_32x32_ten_steps(prec, ic_32x32):
+    """The precision form's stated size: 32^3 x 32^3, 10 steps with the drifting
+    field, density against the FP64 oracle's (tests/golden/make_density_32x32.py):
+    FP32 storage within 1e-5, FP16/BF16 storage within 2e-3 relative L2; in-domain
+    mass plus outflow within 1e-6 (FP32) or 2e-3 of the oracle's."""
+    w, f0 = ic_32x32
+    print("case: density error 32^3x32^3", V.PREC_NAME[prec], flush=True)
+    ref = np.load(GOLDEN_32)
+    hg = V.make_grid(w.n, w.nu, w.L, w.umax)
+    pot = inputs.potential(w)
+    st = V.encode(hg, prec, f0.cuda())
+    ofl = torch.zeros(tuple(w.n), dtype=torch.float64, device="cuda")
+    work = torch.empty(V.vlasov_step_workspace_bytes(hg, prec), dtype=torch.uint8, device="cuda")
+    for n in range(10):
+        gn = torch.from_numpy(inputs.accel_field(w, pot, n * w.dt)).cuda()
+        gnp1 = torch.from_numpy(inputs.accel_field(w, pot, (n + 1) * w.dt)).cuda()
+        st = V.step(st, gn, gnp1, w.dt, outflow=ofl, work=work)
+    rho, _, mass = V.moments(st)
+    torch.cuda.synchronize()
+    rho = rho.cpu().numpy()
+    rel_l2 = np.linalg.norm(rho - ref["rho"]) / np.linalg.norm(ref["rho"])
+    total = float(mass) + float(ofl.sum()) * float(np.prod([w.dx(a) for a in range(3)]))
+    total_ref = float(ref["mass"]) + float(ref["outflow"]) * float(np.prod([w.dx(a) for a in range(3)]))
+    mass_err = abs(total - total_ref) / total_ref
+    print(f"{V.PREC_NAME[prec]}: density rel L2 {rel_l2:.3e}, mass+outflow rel err {mass_err:.3e}")
+    tol = 1e-5 if prec == V.F32 else 2e-3
+    assert rel_l2 <= tol
+    assert mass_err <= (1e-6 if prec == V.F32 else 2e-3)
