@@ -190,29 +190,76 @@ __device__ __forceinline__ float kick_axis(float* lds, float* sout_line, float* 
     return kick_axis_dir<P, NU, PER, AXIS, false>(lds + base, sh, N, sout_line, lmax_line);
 }
 
-// FP64 sums of three values per thread over the work-group (the tree of
-// block_sum for each), in thread 0.
-template <int NT>
-__device__ __forceinline__ void block_sum3(double (&v)[3], double* red)
+// A double moved between lanes by a DPP control (each 32-bit half).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
 {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp((int)u, (int)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(u >> 32), (int)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double read_lane_f64(double v, int lane)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readlane((int)u, lane);
+    const unsigned hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// The sum of v over the wave, the same in every lane: a DPP tree within each
+// 16-lane row (quad permutations, then half-row and row mirrors; partners
+// add the same two partial sums, so every lane of a row holds the same bits),
+// then the four row sums in row order.  Short VALU latencies: the sum sits
+// right before a barrier.
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    v += dpp_f64<0xB1>(v);     // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);     // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);    // row_half_mirror
+    v += dpp_f64<0x140>(v);    // row_mirror
+    return ((read_lane_f64(v, 0) + read_lane_f64(v, 16)) + read_lane_f64(v, 32)) +
+           read_lane_f64(v, 48);
+}
+
+// Outflow of one block, first half: the FP64 sums of the three per-thread
+// line outflows over each wave, written by lane 0 to red[axis][wave].  The
+// barrier that ends the last sweep publishes them.
+template <int NT>
+__device__ __forceinline__ void wave_sums3(const float (&o)[3], double* red)
+{
+    double v[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-        for (int w = 32; w >= 1; w >>= 1) v[k] += __shfl_xor(v[k], w);
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) {
+    for (int k = 0; k < 3; ++k) v[k] = wave_sum_f64((double)o[k]);
+    if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) red[k * (NT / 64) + wave] = v[k];
+        for (int k = 0; k < 3; ++k) red[k * (NT / 64) + (threadIdx.x >> 6)] = v[k];
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+}
+
+// Second half, in wave 0 after that barrier: lane k < 3 adds the wave sums of
+// axis k in wave order, and lane 0 adds the three axes to the cell's total in
+// sweep order (ux, uy, uz), as three separate sweeps would.  prev is the
+// cell's total before this kick, loaded early by lane 0.
+template <int NT>
+__device__ __forceinline__ void outflow_total(const double* red, double prev, double du3,
+                                              double* dst)
+{
+    const int lane = threadIdx.x;
+    const int k = lane < 3 ? lane : 0;
+    double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            double s = 0.0;
-            for (int q = 0; q < NT / 64; ++q) s += red[k * (NT / 64) + q];
-            v[k] = s;
-        }
+    for (int q = 0; q < NT / 64; ++q) s += red[k * (NT / 64) + q];
+    const double s0 = read_lane_f64(s, 0);
+    const double s1 = read_lane_f64(s, 1);
+    const double s2 = read_lane_f64(s, 2);
+    if (lane == 0) {
+        double acc = prev;
+        acc += s0 * du3;
+        acc += s1 * du3;
+        acc += s2 * du3;
+        *dst = acc;
     }
 }
 
@@ -246,7 +293,11 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
     if (next < ncell) R.load(fin, sin, a, next, fresh_tid());
     __syncthreads();
 
+    const bool ofl = a.outflow != nullptr && !PER;
     for (;;) {
+        // the cell's outflow total so far, needed only after the sweeps
+        double prev = 0.0;
+        if (ofl && t == 0) prev = a.outflow[cell];
         float o[3];
         o[0] = kick_axis<P, NU, PER, 0>(lds, nullptr, nullptr, a, tab, cell, g[0], t);
         __syncthreads();
@@ -254,19 +305,9 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
         __syncthreads();
         o[2] = kick_axis<P, NU, PER, 2>(lds, Codec<P>::scaled ? sout + (long)cell * NL + t : nullptr,
                                         lmax + t, a, tab, cell, g[2], t);
+        if (ofl) wave_sums3<NT>(o, red);
         __syncthreads();
-
-        if (a.outflow != nullptr && !PER) {
-            // same order as three separate sweeps: ux, then uy, then uz
-            double v[3] = {(double)o[0], (double)o[1], (double)o[2]};
-            block_sum3<NT>(v, red);
-            if (t == 0) {
-                double acc = a.outflow[cell];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) acc += v[k] * a.du3;
-                a.outflow[cell] = acc;
-            }
-        }
+        if (ofl && t < 64) outflow_total<NT>(red, prev, a.du3, a.outflow + cell);
 
         // store the finished block; each slot is refilled with the next block
         // by the thread that stored it, so no barrier sits in between
