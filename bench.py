@@ -36,10 +36,12 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # where the unlimited interface value passes the Suresh-Huynh test (four
 # products for the value, one new difference, the test, the clamp and the
 # update), 30 more where it fails and the full bounds are built -- about one
-# interface in ten on this workload's velocity profile.  Scaled storage adds
-# the rounding of the block between sweeps and the codec at load and store.
-KICK_OPS_PER_CELL_SWEEP = {0: 14.0 + 0.10 * 30.0, 1: 14.0 + 0.10 * 30.0 + 4.5,
-                           2: 14.0 + 0.10 * 30.0 + 4.5}
+# interface in ten on this workload's velocity profile.  Scaled storage keeps
+# FP32 values between the three sweeps and adds only the codec, once per kick:
+# decoding (convert, scale) and encoding (largest |value|, scale, convert),
+# five operations per cell, a third of them per sweep.
+KICK_OPS_PER_CELL_SWEEP = {0: 14.0 + 0.10 * 30.0, 1: 14.0 + 0.10 * 30.0 + 5.0 / 3.0,
+                           2: 14.0 + 0.10 * 30.0 + 5.0 / 3.0}
 
 
 def _log(msg):
