@@ -144,18 +144,65 @@ struct GlobalWriter {
     }
 };
 
+// Raw buffer access for rows whose address is wave-uniform: the row's start
+// goes into a buffer resource (scalar registers, rebuilt per row by a few
+// scalar instructions) and each lane supplies only its fixed byte offset in a
+// VGPR, so a row access costs no vector address arithmetic.  The resource
+// covers exactly the bytes from the row start that the wave may touch; an
+// access beyond them reads zero and writes nothing.
+__device__ __forceinline__ unsigned row_span_bytes(long b)
+{
+    return b > 0xFFFFFFFFL ? 0xFFFFFFFFu : (unsigned)b;
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* p, unsigned bytes)
+{
+    // word 3 = 0x00020000: the gfx9 raw-buffer format (32-bit data format)
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <class T, int V>
+__device__ __forceinline__ Pack<T, V> buffer_load_pack(__amdgpu_buffer_rsrc_t rs, unsigned off)
+{
+    constexpr int B = (int)sizeof(T) * V;
+    static_assert(B == 2 || B == 4 || B == 8 || B == 16, "row piece of 2, 4, 8 or 16 bytes");
+    if constexpr (B == 16) return __builtin_bit_cast(Pack<T, V>, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+    else if constexpr (B == 8) return __builtin_bit_cast(Pack<T, V>, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+    else if constexpr (B == 4) return __builtin_bit_cast(Pack<T, V>, __builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+    else return __builtin_bit_cast(Pack<T, V>, __builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0));
+}
+
+template <class T, int V>
+__device__ __forceinline__ void buffer_store_pack(const Pack<T, V>& q, __amdgpu_buffer_rsrc_t rs, unsigned off)
+{
+    constexpr int B = (int)sizeof(T) * V;
+    static_assert(B == 2 || B == 4 || B == 8 || B == 16, "row piece of 2, 4, 8 or 16 bytes");
+    if constexpr (B == 16) {
+        using W = __attribute__((ext_vector_type(4))) unsigned;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(W, q), rs, (int)off, 0, 0);
+    } else if constexpr (B == 8) {
+        using W = __attribute__((ext_vector_type(2))) unsigned;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, q), rs, (int)off, 0, 0);
+    } else if constexpr (B == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, q), rs, (int)off, 0, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, q), rs, (int)off, 0, 0);
+    }
+}
+
 // Rows of the lines of one wave when every lane visits the same rows (one
 // integer shift and one walk direction over the wave; periodic lines): the
 // row index and the row's address are scalar work, and a lane only adds its
-// fixed 32-bit offset within the row, so no row access costs vector address
-// arithmetic.
+// fixed byte offset within the row (buffer addressing above).
 template <int P, int V>
 struct URowReader {
     using T = typename Codec<P>::T;
     const T* base;        // row 0 of the wave's first element (uniform)
     const float* sbase;   // its scale (uniform; scaled storage)
-    unsigned loff;        // this lane's element offset within a row
-    unsigned soff;        // this lane's scale offset within a row
+    unsigned loff;        // this lane's byte offset within a row
+    unsigned soff;        // this lane's scale byte offset within a row
+    unsigned nbytes;      // bytes from base to the end of its row
+    unsigned sbytes;      // the same for the scales
     long stride;          // elements between rows
     long sstride;         // scales between rows
     int M;
@@ -171,15 +218,14 @@ struct URowReader {
     }
     __device__ void next(float* x)
     {
-        // scalar row address + this lane's 32-bit byte offset: the form the
-        // global loads take with an SGPR base and a VGPR offset
-        const char* row = reinterpret_cast<const char*>(base + (long)phys * stride);
         float sc = 1.0f;
-        if (Codec<P>::scaled) {
-            const char* srow = reinterpret_cast<const char*>(sbase + (long)phys * sstride);
-            sc = *reinterpret_cast<const float*>(srow + (unsigned)(soff * sizeof(float)));
-        }
-        load_row<P, V>(reinterpret_cast<const T*>(row + (unsigned)(loff * sizeof(T))), sc, x);
+        if (Codec<P>::scaled)
+            sc = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                     row_rsrc(sbase + (long)phys * sstride, sbytes), (int)soff, 0, 0));
+        const Pack<T, V> q = buffer_load_pack<T, V>(row_rsrc(base + (long)phys * stride, nbytes), loff);
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            x[v] = Codec<P>::scaled ? Codec<P>::dec(q.v[v]) * sc : Codec<P>::dec(q.v[v]);
         phys += dir;
         if (phys == M) phys = 0;
         else if (phys < 0) phys = M - 1;
@@ -193,6 +239,8 @@ struct URowWriter {
     float* sbase;
     unsigned loff;
     unsigned soff;
+    unsigned nbytes;
+    unsigned sbytes;
     long stride;
     long sstride;
     int M;
@@ -202,21 +250,24 @@ struct URowWriter {
     __device__ void put(int i, const float* x)
     {
         const long p = dir > 0 ? i : M - 1 - i;
-        char* row = reinterpret_cast<char*>(base + p * stride);
-        T* dst = reinterpret_cast<T*>(row + (unsigned)(loff * sizeof(T)));
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(base + p * stride, nbytes);
+        Pack<T, V> q;
         if (Codec<P>::scaled) {
             float m = 0.0f;
 #pragma unroll
             for (int v = 0; v < V; ++v) m = fmaxf(m, fabsf(x[v]));
             m = GC > 0 ? group_max_nonneg<GC>(m) : group_max(m, G);
             const float inv = inv_scale(m);
-            store_row<P, V>(dst, x, inv);
-            if ((threadIdx.x & (G - 1)) == 0) {
-                char* srow = reinterpret_cast<char*>(sbase + p * sstride);
-                *reinterpret_cast<float*>(srow + (unsigned)(soff * sizeof(float))) = m;
-            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) q.v[v] = quantize<P>(x[v], inv);
+            buffer_store_pack<T, V>(q, rs, loff);
+            if ((threadIdx.x & (G - 1)) == 0)
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, m),
+                                                      row_rsrc(sbase + p * sstride, sbytes), (int)soff, 0, 0);
         } else {
-            store_row<P, V>(dst, x, 1.0f);
+#pragma unroll
+            for (int v = 0; v < V; ++v) q.v[v] = Codec<P>::enc(x[v]);
+            buffer_store_pack<T, V>(q, rs, loff);
         }
     }
 };

@@ -81,18 +81,22 @@ __global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __
         // SGPR bases and each access adds only the lane's 32-bit offset)
         const long ub = uniform_long(o0 * (long)M * a.I + k0);
         const long usb = uniform_long(o0 * (long)M * sI + k0 / a.nuz);
-        const unsigned loff = (unsigned)(k - k0);
-        const unsigned soff = (unsigned)(k / a.nuz - k0 / a.nuz);
+        const unsigned loff = (unsigned)((k - k0) * (long)sizeof(typename Codec<P>::T));
+        const unsigned soff = (unsigned)((k / a.nuz - k0 / a.nuz) * (long)sizeof(float));
+        // bytes from the wave's first element (scale) to the end of its row
+        const unsigned nb = (unsigned)uniform_sgpr(
+            (int)row_span_bytes((a.I - k0) * (long)sizeof(typename Codec<P>::T)));
+        const unsigned snb = (unsigned)uniform_sgpr((int)row_span_bytes((sI - k0 / a.nuz) * (long)sizeof(float)));
         LineShift shu = sh;
         shu.N = uniform_sgpr(sh.N);
         if (one_dir) {
             const int dir = uniform_sgpr(sh.neg ? -1 : 1);
-            URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, a.I, sI, M, dir, 0};
-            URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, a.I, sI, M, dir, a.G};
+            URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, dir, 0};
+            URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, dir, a.G};
             walk_uniform<V, MT>(rd, wr, M, shu, true, nullptr);
         } else {
-            URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, a.I, sI, M, 1, 0};
-            URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, a.I, sI, M, 1, a.G};
+            URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, 1, 0};
+            URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, 1, a.G};
             walk_mixed<V, MT>(rd, wr, M, uniform_sgpr(Ns), shu);
         }
     } else if (one_dir) {
