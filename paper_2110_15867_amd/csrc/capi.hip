@@ -96,6 +96,37 @@ double position_shift(const vlasov_grid* g, int a, long j, double dt_over_a2)
     return u * factor;
 }
 
+// Integer part of a periodic line's shift in its upwind frame, as the
+// kernels split it (floor of |s|, reduced mod M), and its direction.
+void split_integer(double s, int M, int* N, bool* neg)
+{
+    const double n = (s >= 0.0) ? floor(s) : ceil(s);
+    *neg = s < 0.0;
+    *N = (int)fmod(*neg ? -n : n, (double)M);
+}
+
+// Whether the z sweep can pair the two halves of each uz-line in one lane
+// (see k_position_pair): every line of the upper half must move up and every
+// line of the lower half down, all by less than one cell; the half length
+// must divide the wave, a row must hold whole waves of lanes and the line
+// length must have a compiled walk.  Returns 1 when it can, else 0.
+int pair_mode(const PosArgs& a)
+{
+    const long nuz = a.nuz;
+    const long H = nuz / 2;
+    if (a.V != 1 || a.pst != 1 || a.nshift != nuz || nuz % 2 != 0) return 0;
+    if (H != 8 && H != 16 && H != 32) return 0;
+    if ((a.I / 2) % 64 != 0) return 0;
+    if (a.M != 16 && a.M != 32 && a.M != 64) return 0;
+    for (long j = 0; j < nuz; ++j) {
+        int n;
+        bool neg;
+        split_integer(a.shift[j], a.M, &n, &neg);
+        if (n != 0 || neg != (j < H)) return 0;
+    }
+    return 1;
+}
+
 int make_pos_args(const vlasov_grid* g, const Dims& d, int axis, double dt_over_a2, PosArgs& a)
 {
     if (!isfinite(dt_over_a2)) return VLASOV_ERR_NONFINITE;
@@ -116,6 +147,7 @@ int make_pos_args(const vlasov_grid* g, const Dims& d, int axis, double dt_over_
         a.shift[j] = position_shift(g, axis, j, dt_over_a2);
         if (!isfinite(a.shift[j])) return VLASOV_ERR_NONFINITE;
     }
+    if (axis == 2) a.pair = pair_mode(a);
     return VLASOV_OK;
 }
 

@@ -19,6 +19,7 @@ struct PosArgs {
     long nuz;        // length of a uz-line (scale granularity)
     int V;           // adjacent inner elements per thread
     int G;           // lanes per uz-line (scaled storage)
+    int pair;        // z sweep with the halves of each uz-line paired per lane (0: no)
     double shift[kMaxShiftTable];   // s_j = u_j dt a^-2 / dx per velocity index
 };
 

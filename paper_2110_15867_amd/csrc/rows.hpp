@@ -272,6 +272,111 @@ struct URowWriter {
     }
 };
 
+// The value held by lane l ^ (H/2), for aligned groups of H lanes: a DPP
+// row rotation by 8 for H = 16, an LDS-free swizzle otherwise.
+template <int H>
+__device__ __forceinline__ float xor_half(float v)
+{
+    static_assert(H == 8 || H == 16 || H == 32, "uz-line halves of 4, 8 or 16 lanes");
+    if constexpr (H == 16)
+        return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x128, 0xF, 0xF, true));
+    else
+        return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), ((H / 2) << 10) | 0x1F));
+}
+
+// Rows of the paired walk.  A uz-line of 2H values is held by H lanes; the
+// wave reads (and writes) whole rows of 64/H uz-lines, two adjacent values
+// per lane (coalesced, one access per row), and swaps values between lane g
+// and g ^ (H/2) of each group so that lane g holds one value of each half:
+//   g < H/2:  lower half value 2g,        upper half value 2g + H
+//   g >= H/2: lower half value 2g - H + 1, upper half value 2g + 1.
+// The upper half is line A (moving up), the lower half line B.
+template <int P, int H>
+struct PairRowReader {
+    using T = typename Codec<P>::T;
+    const T* base;        // row 0 of the wave's first uz-line (uniform)
+    const float* sbase;   // its scale (uniform; scaled storage)
+    unsigned off;         // this lane's byte offset within a row (two values)
+    unsigned soff;        // byte offset of its uz-line's scale within a scale row
+    unsigned nbytes;      // bytes from base to the end of its row
+    unsigned sbytes;
+    long stride;          // elements between rows
+    long sstride;         // scales between rows
+    int M;
+    bool lo;              // lane g < H/2
+    int phys;             // uniform
+
+    __device__ void seek(int r)
+    {
+        int q = r % M;
+        if (q < 0) q += M;
+        phys = q;
+    }
+    __device__ void next(float* x)
+    {
+        float sc = 1.0f;
+        if (Codec<P>::scaled)
+            sc = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                     row_rsrc(sbase + (long)phys * sstride, sbytes), (int)soff, 0, 0));
+        const Pack<T, 2> q = buffer_load_pack<T, 2>(row_rsrc(base + (long)phys * stride, nbytes), off);
+        float v0 = Codec<P>::dec(q.v[0]);
+        float v1 = Codec<P>::dec(q.v[1]);
+        if (Codec<P>::scaled) {
+            v0 *= sc;
+            v1 *= sc;
+        }
+        const float p0 = xor_half<H>(v0);
+        const float p1 = xor_half<H>(v1);
+        x[0] = lo ? p0 : v1;          // upper half: line A
+        x[1] = lo ? v0 : p1;          // lower half: line B
+        phys += 1;
+        if (phys == M) phys = 0;
+    }
+};
+
+// The inverse exchange, then one coalesced store per row; with scaled
+// storage the uz-line's scale is the largest |value| over its H lanes (two
+// values each).
+template <int P, int H>
+struct PairRowWriter {
+    using T = typename Codec<P>::T;
+    T* base;
+    float* sbase;
+    unsigned off;
+    unsigned soff;
+    unsigned nbytes;
+    unsigned sbytes;
+    long stride;
+    long sstride;
+    bool lo;
+
+    __device__ void put(int i, float xa, float xb)
+    {
+        // xa: upper half value, xb: lower half value of this lane
+        const float qa = xor_half<H>(xa);
+        const float qb = xor_half<H>(xb);
+        const float s0 = lo ? xb : qa;    // value 2g
+        const float s1 = lo ? qb : xa;    // value 2g + 1
+        const __amdgpu_buffer_rsrc_t rs = row_rsrc(base + (long)i * stride, nbytes);
+        Pack<T, 2> q;
+        if (Codec<P>::scaled) {
+            float m = fmaxf(fabsf(xa), fabsf(xb));
+            m = group_max_nonneg<H>(m);
+            const float inv = inv_scale(m);
+            q.v[0] = quantize<P>(s0, inv);
+            q.v[1] = quantize<P>(s1, inv);
+            if ((threadIdx.x & (H - 1)) == 0)
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, m),
+                                                      row_rsrc(sbase + (long)i * sstride, sbytes),
+                                                      (int)soff, 0, 0);
+        } else {
+            q.v[0] = Codec<P>::enc(s0);
+            q.v[1] = Codec<P>::enc(s1);
+        }
+        buffer_store_pack<T, 2>(q, rs, off);
+    }
+};
+
 // Rows of one line held in LDS (already decoded to FP32), `stride` floats
 // apart.
 struct LdsReader {

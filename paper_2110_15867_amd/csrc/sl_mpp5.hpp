@@ -508,4 +508,106 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
     }
 }
 
+// ---------------------------------------------------------------------------
+// Paired walker: each lane updates two periodic lines whose rows it reads
+// and writes together — line A moving up by less than one cell (shift in
+// [0, 1)), line B moving down by less than one cell (shift in (-1, 0)) — so
+// neither needs a per-lane select between upwind stencils.  The reader hands
+// out each row's A and B values (x[0], x[1]); the writer takes both outputs.
+//   A, upwind frame as is (walk_uniform's arithmetic, to the bit):
+//     out_i = x_i - (Phi_i - Phi_{i-1}),  Phi_k = flux through k+1/2 from
+//     cells k-2 .. k+2 (rows -3 .. 1 first, then row i+2 at step i).
+//   B, upwind frame mirrored, walked forward: G_k = flux leaving cell k
+//   through k-1/2, its stencil a..e being cells k+2 .. k-2 and its
+//   differences x_{k+1}-x_{k+2}, x_k-x_{k+1}, x_{k-1}-x_k, x_{k-2}-x_{k-1}
+//   (the subtractions walk_uniform does in the mirrored frame), and
+//     out_i = x_i + (G_{i+1} - G_i)    (rows -2 .. 2 first, then row i+3),
+//   the mirrored walk's x - (G_i - G_{i+1}) to the bit (a rounded difference
+//   changes sign exactly).
+// B needs each row one step before A, so a row is read once, at B's step,
+// and A's value waits one step in a register.  MT (the line length) is
+// fixed at compile time; rows 0..2, read first, serve again as rows M..M+2.
+// ---------------------------------------------------------------------------
+template <int MT, class Reader, class Writer>
+__device__ __forceinline__ void walk_pair(Reader& rd, Writer& wr, const LineShift& sa,
+                                          const LineShift& sb)
+{
+    constexpr int M = MT;
+    constexpr int PD = 8;
+    constexpr int L = M - 3;                      // rows the loop reads
+    static_assert(MT > 3 + PD, "line too short for the paired walk");
+    float a[5], da[4], phia;      // A: window x_{j-2..j+2}, forward differences
+    float b[5], mb[4], gb;        // B: window x_{k-2..k+2}, md[q] = w[q] - w[q+1]
+    float head[3][2];
+    float carry;                  // A's value of the row read last
+    rd.seek(-3);
+    {
+        float x[2];
+        rd.next(x);                                // row -3 (A only)
+        a[0] = x[0];
+#pragma unroll
+        for (int q = 1; q < 6; ++q) {              // rows -2 .. 2
+            rd.next(x);
+            if (q < 5) a[q] = x[0];
+            else carry = x[0];
+            b[q - 1] = x[1];
+            if (q >= 3) {
+                head[q - 3][0] = x[0];
+                head[q - 3][1] = x[1];
+            }
+        }
+    }
+    RowPipe<2, PD, Reader> pipe(rd);
+    pipe.prime(L);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        da[q] = a[q + 1] - a[q];
+        mb[q] = b[q] - b[q + 1];
+    }
+    phia = flux_mag(Stencil{a[0], a[1], a[2], a[3], a[4], da[0], da[1], da[2], da[3]}, sa);
+    gb = flux_mag(Stencil{b[4], b[3], b[2], b[1], b[0], mb[3], mb[2], mb[1], mb[0]}, sb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        a[q] = a[q + 1];
+        b[q] = b[q + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        da[q] = da[q + 1];
+        mb[q] = mb[q + 1];
+    }
+#pragma unroll MT
+    for (int i = 0; i < M; ++i) {
+        float x[2];                                // row i + 3
+        if (i >= L) {
+            x[0] = head[i - L][0];
+            x[1] = head[i - L][1];
+        } else {
+            pipe.take(i, L, x);
+        }
+        a[4] = carry;                              // row i + 2
+        carry = x[0];
+        b[4] = x[1];
+        da[3] = a[4] - a[3];
+        mb[3] = b[3] - b[4];
+        const float pa_new = flux_mag(Stencil{a[0], a[1], a[2], a[3], a[4], da[0], da[1], da[2], da[3]}, sa);
+        const float gb_new = flux_mag(Stencil{b[4], b[3], b[2], b[1], b[0], mb[3], mb[2], mb[1], mb[0]}, sb);
+        const float ra_out = a[2] - (pa_new - phia);
+        const float rb_out = b[1] + (gb_new - gb);
+        phia = pa_new;
+        gb = gb_new;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = a[q + 1];
+            b[q] = b[q + 1];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            da[q] = da[q + 1];
+            mb[q] = mb[q + 1];
+        }
+        wr.put(i, ra_out, rb_out);
+    }
+}
+
 }  // namespace vlasov

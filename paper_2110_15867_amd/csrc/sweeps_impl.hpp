@@ -112,6 +112,54 @@ __global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __
 }
 
 // ---------------------------------------------------------------------------
+// z sweep with paired lines.  The shift follows the contiguous u_z index;
+// the host takes this path only when every line of the upper half of a
+// uz-line (u_z > 0) moves up and every line of the lower half moves down,
+// all by less than one cell, H = nu_z / 2 divides the wave and a row holds
+// whole waves of lanes.  Each lane then owns one line of each half (see
+// PairRowReader), every wave visits uniform rows (buffer addressing, one
+// coalesced access per row) and runs two select-free walks.  Results are
+// the bits of the per-lane mixed walk.
+// ---------------------------------------------------------------------------
+template <int P, int MT, int H>
+__global__ void __launch_bounds__(256) k_position_pair(const typename Codec<P>::T* __restrict__ fin,
+                                                       const float* __restrict__ sin,
+                                                       typename Codec<P>::T* __restrict__ fout,
+                                                       float* __restrict__ sout, PosArgs a)
+{
+    using T = typename Codec<P>::T;
+    constexpr int NUZ = 2 * H;
+    const long IP = a.I / 2;                      // lanes per row
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.O * IP) return;                    // whole waves (IP % 64 == 0)
+    const long o = t / IP;
+    const long kp = t - o * IP;
+    const long q = kp / H;                        // uz-line within the row
+    const int g = (int)(kp - q * H);              // lane within the uz-line
+    const bool lo = g < H / 2;
+    const int up = lo ? 2 * g + H : 2 * g + 1;    // velocity index of this lane's A line
+    const int dn = lo ? 2 * g : 2 * g - H + 1;    // ... and of its B line
+    const LineShift sa = split_shift(a.shift[up], MT, true);
+    const LineShift sb = split_shift(a.shift[dn], MT, true);
+
+    const long t0 = t - (threadIdx.x & 63);       // lane 0 of this wave
+    const long o0 = t0 / IP;
+    const long q0 = (t0 - o0 * IP) / H;
+    const long sI = a.I / NUZ;
+    const long ub = uniform_long(o0 * (long)MT * a.I + q0 * NUZ);
+    const long usb = uniform_long(o0 * (long)MT * sI + q0);
+    const unsigned off = (unsigned)(((q - q0) * NUZ + 2 * g) * (long)sizeof(T));
+    const unsigned soff = (unsigned)((q - q0) * (long)sizeof(float));
+    const unsigned nb = (unsigned)uniform_sgpr((int)row_span_bytes((a.I - q0 * NUZ) * (long)sizeof(T)));
+    const unsigned snb = (unsigned)uniform_sgpr((int)row_span_bytes((sI - q0) * (long)sizeof(float)));
+    PairRowReader<P, H> rd{fin + ub, Codec<P>::scaled ? sin + usb : nullptr, off, soff, nb, snb,
+                           a.I, sI, MT, lo, 0};
+    PairRowWriter<P, H> wr{fout + ub, Codec<P>::scaled ? sout + usb : nullptr, off, soff, nb, snb,
+                           a.I, sI, lo};
+    walk_pair<MT>(rd, wr, sa, sb);
+}
+
+// ---------------------------------------------------------------------------
 // Velocity sweeps ux, uy: one work-group per spatial cell
 // ---------------------------------------------------------------------------
 template <int P, int V, int MT>
@@ -282,6 +330,23 @@ inline hipError_t launch_position_v(const void* fin, const float* sin, void* fou
     const long total = a.O * (a.I / V);
     const unsigned blocks = (unsigned)((total + 255) / 256);
     if (total == 0) return hipSuccess;
+    // Paired z walks for FP16/BF16 storage, where the z sweep is bound by
+    // its vector ALU work; with FP32 storage it is bound by memory and the
+    // per-lane walk, with half the bytes per wave row, measured faster.
+    if constexpr (V == 1 && Codec<P>::scaled) if (a.pair != 0) {
+        // the host checked: nu_z in {16, 32, 64}, M in {16, 32, 64}
+        const unsigned pblocks = (unsigned)((a.O * (a.I / 2) + 255) / 256);
+#define VL_PAIR(MTV, HV) \
+    hipLaunchKernelGGL((k_position_pair<P, MTV, HV>), dim3(pblocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a)
+#define VL_PAIR_M(HV) \
+    switch (a.M) { case 16: VL_PAIR(16, HV); break; case 32: VL_PAIR(32, HV); break; default: VL_PAIR(64, HV); break; }
+        if (a.nuz == 16) { VL_PAIR_M(8) }
+        else if (a.nuz == 32) { VL_PAIR_M(16) }
+        else { VL_PAIR_M(32) }
+#undef VL_PAIR_M
+#undef VL_PAIR
+        return hipGetLastError();
+    }
     // uz-lines of 32 values (the usual velocity block) get the compile-time
     // group size of the scale reduction
     constexpr int G32 = Codec<P>::scaled ? 32 / V : 0;
