@@ -148,6 +148,7 @@ int make_pos_args(const vlasov_grid* g, const Dims& d, int axis, double dt_over_
         if (!isfinite(a.shift[j])) return VLASOV_ERR_NONFINITE;
     }
     if (axis == 2) a.pair = pair_mode(a);
+    a.skew = axis != 2;
     return VLASOV_OK;
 }
 

@@ -20,6 +20,7 @@ struct PosArgs {
     int V;           // adjacent inner elements per thread
     int G;           // lanes per uz-line (scaled storage)
     int pair;        // z sweep with the halves of each uz-line paired per lane (0: no)
+    int skew;        // waves start their walks at different rows (1) or all at row 0
     double shift[kMaxShiftTable];   // s_j = u_j dt a^-2 / dx per velocity index
 };
 

@@ -207,10 +207,12 @@ struct URowReader {
     long sstride;         // scales between rows
     int M;
     int dir;              // uniform
+    int r0;               // frame rotation (uniform, 0 <= r0 < M; see URowWriter)
     int phys;             // uniform
 
     __device__ void seek(int r)
     {
+        r += r0;
         int q = dir > 0 ? r : M - 1 - r;
         q %= M;
         if (q < 0) q += M;
@@ -245,11 +247,18 @@ struct URowWriter {
     long sstride;
     int M;
     int dir;              // uniform
+    int r0;               // frame rotation (uniform, 0 <= r0 < M)
     int G;                // lanes per uz-line (scaled storage)
 
+    // A periodic line may be walked from any frame row: frame row i is row
+    // i + r0 (mod M) of the unrotated frame, with the same arithmetic for
+    // every output.  Waves that start at different rows spread their
+    // concurrent accesses over more of the memory system.
     __device__ void put(int i, const float* x)
     {
-        const long p = dir > 0 ? i : M - 1 - i;
+        int f = i + r0;
+        if (f >= M) f -= M;
+        const long p = dir > 0 ? f : M - 1 - f;
         const __amdgpu_buffer_rsrc_t rs = row_rsrc(base + p * stride, nbytes);
         Pack<T, V> q;
         if (Codec<P>::scaled) {

@@ -89,14 +89,16 @@ __global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __
         const unsigned snb = (unsigned)uniform_sgpr((int)row_span_bytes((sI - k0 / a.nuz) * (long)sizeof(float)));
         LineShift shu = sh;
         shu.N = uniform_sgpr(sh.N);
+        // x and y: each wave starts its walk at its own row (see URowWriter)
+        const int r0 = a.skew ? uniform_sgpr((int)(((t0 >> 6) * 17) % M)) : 0;
         if (one_dir) {
             const int dir = uniform_sgpr(sh.neg ? -1 : 1);
-            URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, dir, 0};
-            URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, dir, a.G};
+            URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, dir, r0, 0};
+            URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, dir, r0, a.G};
             walk_uniform<V, MT>(rd, wr, M, shu, true, nullptr);
         } else {
-            URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, 1, 0};
-            URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, 1, a.G};
+            URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, 1, r0, 0};
+            URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, 1, r0, a.G};
             walk_mixed<V, MT>(rd, wr, M, uniform_sgpr(Ns), shu);
         }
     } else if (one_dir) {
