@@ -11,12 +11,14 @@ __all__ = ["inputs", "vlasov"]
 
 
 def __getattr__(name):
-    if name in ("vlasov", "inputs"):
-        import importlib
-
-        return importlib.import_module(f"{__name__}.{name}")
     import importlib
+    import importlib.util
 
+    # submodules (vlasov, inputs, autograd, build) import on first use; only
+    # other names are looked up in the binding, so building the library does
+    # not need a built library
+    if importlib.util.find_spec(f"{__name__}.{name}") is not None:
+        return importlib.import_module(f"{__name__}.{name}")
     mod = importlib.import_module(f"{__name__}.vlasov")
     if hasattr(mod, name):
         return getattr(mod, name)
