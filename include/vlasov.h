@@ -176,6 +176,24 @@ int vlasov_step(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, const
                 double* outflow, void* stream);
 
 /*
+ * vlasov_step, also returning the velocity moments of f^{n+1} (section
+ * 5.1.3) as vlasov_moments defines them: rho [nx][ny][nz] (required) and
+ * umean [3][nx][ny][nz] (may be NULL), FP64 device arrays.  Where the last
+ * kick runs fused, the moments are summed while it stores each cell's block
+ * (from the stored values: decoded codes for FP16/BF16), so no pass reads
+ * f^{n+1} again; otherwise they come from a moments pass over f_out.  The
+ * summation order differs from vlasov_moments', so the two agree to FP64
+ * rounding, not to the bit.  f_out is the bits vlasov_step writes.
+ * Errors: as vlasov_step; VLASOV_ERR_NULL for a NULL rho; VLASOV_ERR_ALIAS
+ * when rho or umean overlap each other, f_out or work.
+ */
+int vlasov_step_moments(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc,
+                        const void* f_in, const float* scale_in, void* f_out, float* scale_out,
+                        const float* g_n, const float* g_np1, double dt, double a2inv,
+                        void* work, size_t work_bytes, double* outflow, double* rho,
+                        double* umean, void* stream);
+
+/*
  * Velocity moments per spatial cell (section 5.1.3), accumulated in FP64:
  *   rho[c]      = sum_u f du^3
  *   umean[a][c] = sum_u u_a f du^3 / rho[c]  (0 where rho[c] = 0); may be NULL

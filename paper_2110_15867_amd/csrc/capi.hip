@@ -214,9 +214,35 @@ size_t lds_limit()
 
 // D_uz D_uy D_ux over dt with one field: fused in LDS where the velocity
 // block fits, otherwise three single sweeps through `mid` buffers.
+// Moments of f (arguments checked by the caller): rho, umean per cell, and the
+// total mass when `mass` is given.
+int run_moments(const vlasov_grid* g, const Dims& d, int prec, const void* f, const float* scale,
+                double* rho, double* umean, double* mass, hipStream_t st)
+{
+    MomArgs a;
+    memset(&a, 0, sizeof(a));
+    a.cells = d.cells;
+    a.Nu = d.Nu;
+    a.nuz = d.nu[2];
+    a.du3 = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        a.nu[k] = (int)d.nu[k];
+        a.umin[k] = -g->umax[k];
+        a.du[k] = 2.0 * g->umax[k] / g->nu[k];
+        a.du3 *= a.du[k];
+    }
+    a.rho = rho;
+    a.umean = umean;
+    int rc = from_hip(launch_moments(prec, f, scale, a, st));
+    if (rc || mass == nullptr) return rc;
+    const double dx3 = (g->L[0] / g->n[0]) * (g->L[1] / g->n[1]) * (g->L[2] / g->n[2]);
+    return from_hip(launch_sum(rho, d.cells, dx3, mass, st));
+}
+
 int run_kick(const vlasov_grid* g, const Dims& d, int prec, int vbc, const void* fin,
              const float* sin, void* fout, float* sout, void* midf, float* mids,
-             const float* field, double dt, double* outflow, KickShift* shifts, hipStream_t st)
+             const float* field, double dt, double* outflow, KickShift* shifts, hipStream_t st,
+             double* rho = nullptr, double* umean = nullptr)
 {
     if (!isfinite(dt)) return VLASOV_ERR_NONFINITE;
     int nu[3] = {(int)d.nu[0], (int)d.nu[1], (int)d.nu[2]};
@@ -234,6 +260,12 @@ int run_kick(const vlasov_grid* g, const Dims& d, int prec, int vbc, const void*
         a.du3 = (2.0 * g->umax[0] / g->nu[0]) * (2.0 * g->umax[1] / g->nu[1]) *
                 (2.0 * g->umax[2] / g->nu[2]);
         a.cells = d.cells;
+        a.rho = rho;
+        a.umean = umean;
+        for (int k = 0; k < 3; ++k) {
+            a.umin[k] = -g->umax[k];
+            a.du[k] = 2.0 * g->umax[k] / g->nu[k];
+        }
         return from_hip(launch_kick(prec, fin, sin, fout, sout, a, shifts, st));
     }
     if (midf == nullptr) return VLASOV_ERR_WORKSPACE;
@@ -241,7 +273,9 @@ int run_kick(const vlasov_grid* g, const Dims& d, int prec, int vbc, const void*
     if (rc) return rc;
     rc = run_velocity(g, d, 1, prec, vbc, fout, sout, midf, mids, field, dt, outflow, st);
     if (rc) return rc;
-    return run_velocity(g, d, 2, prec, vbc, midf, mids, fout, sout, field, dt, outflow, st);
+    rc = run_velocity(g, d, 2, prec, vbc, midf, mids, fout, sout, field, dt, outflow, st);
+    if (rc || rho == nullptr) return rc;
+    return run_moments(g, d, prec, fout, sout, rho, umean, nullptr, st);
 }
 
 int advect_position(const vlasov_grid* g, int axis, int prec, const void* fin, const float* sin,
@@ -359,10 +393,10 @@ size_t vlasov_step_workspace_bytes(const vlasov_grid* grid, vlasov_prec prec)
     return shift_table_offset(d, prec) + align_up((size_t)(3 * d.cells) * sizeof(KickShift));
 }
 
-int vlasov_step(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
-                const float* sin, void* fout, float* sout, const float* g_n, const float* g_np1,
-                double dt, double a2inv, void* work, size_t work_bytes, double* outflow,
-                void* stream)
+static int step_impl(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
+                     const float* sin, void* fout, float* sout, const float* g_n,
+                     const float* g_np1, double dt, double a2inv, void* work, size_t work_bytes,
+                     double* outflow, double* rho, double* umean, void* stream)
 {
     Dims d;
     if (g == nullptr) return VLASOV_ERR_NULL;
@@ -399,15 +433,46 @@ int vlasov_step(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const vo
     if ((rc = run_position(g, d, 1, prec, wf, ws, fout, sout, dta, st))) return rc;
     if ((rc = run_position(g, d, 0, prec, fout, sout, wf, ws, dta, st))) return rc;
     if ((rc = run_kick(g, d, prec, vbc, wf, ws, fout, sout, nullptr, nullptr, g_np1, h, outflow,
-                       tab, st)) == VLASOV_ERR_WORKSPACE) {
+                       tab, st, rho, umean)) == VLASOV_ERR_WORKSPACE) {
         // unfused last kick: x result is in work; go work -> out -> work -> out
         if ((rc = run_velocity(g, d, 0, prec, vbc, wf, ws, fout, sout, g_np1, h, outflow, st)))
             return rc;
         if ((rc = run_velocity(g, d, 1, prec, vbc, fout, sout, wf, ws, g_np1, h, outflow, st)))
             return rc;
         rc = run_velocity(g, d, 2, prec, vbc, wf, ws, fout, sout, g_np1, h, outflow, st);
+        if (rc == VLASOV_OK && rho != nullptr)
+            rc = run_moments(g, d, prec, fout, sout, rho, umean, nullptr, st);
     }
     return rc;
+}
+
+int vlasov_step(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
+                const float* sin, void* fout, float* sout, const float* g_n, const float* g_np1,
+                double dt, double a2inv, void* work, size_t work_bytes, double* outflow,
+                void* stream)
+{
+    return step_impl(g, prec, vbc, fin, sin, fout, sout, g_n, g_np1, dt, a2inv, work, work_bytes,
+                     outflow, nullptr, nullptr, stream);
+}
+
+int vlasov_step_moments(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
+                        const float* sin, void* fout, float* sout, const float* g_n,
+                        const float* g_np1, double dt, double a2inv, void* work,
+                        size_t work_bytes, double* outflow, double* rho, double* umean,
+                        void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (rho == nullptr) return VLASOV_ERR_NULL;
+    const size_t nb = (size_t)d.cells * sizeof(double);
+    if (umean != nullptr && overlap(rho, nb, umean, 3 * nb)) return VLASOV_ERR_ALIAS;
+    const size_t fb = (size_t)d.total * elem_bytes(prec);
+    if (overlap(fout, fb, rho, nb) || overlap(fout, fb, umean, 3 * nb) ||
+        overlap(work, work_bytes, rho, nb) || overlap(work, work_bytes, umean, 3 * nb))
+        return VLASOV_ERR_ALIAS;
+    return step_impl(g, prec, vbc, fin, sin, fout, sout, g_n, g_np1, dt, a2inv, work, work_bytes,
+                     outflow, rho, umean, stream);
 }
 
 int vlasov_kick(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
@@ -466,25 +531,7 @@ int vlasov_moments(const vlasov_grid* g, vlasov_prec prec, const void* f, const 
     if (umean != nullptr && overlap(rho, nb, umean, 3 * nb)) return VLASOV_ERR_ALIAS;
     if (mass != nullptr && (overlap(mass, 8, rho, nb) || overlap(mass, 8, umean, 3 * nb)))
         return VLASOV_ERR_ALIAS;
-    MomArgs a;
-    memset(&a, 0, sizeof(a));
-    a.cells = d.cells;
-    a.Nu = d.Nu;
-    a.nuz = d.nu[2];
-    a.du3 = 1.0;
-    for (int k = 0; k < 3; ++k) {
-        a.nu[k] = (int)d.nu[k];
-        a.umin[k] = -g->umax[k];
-        a.du[k] = 2.0 * g->umax[k] / g->nu[k];
-        a.du3 *= a.du[k];
-    }
-    a.rho = rho;
-    a.umean = umean;
-    hipStream_t st = (hipStream_t)stream;
-    int rc = from_hip(launch_moments(prec, f, scale, a, st));
-    if (rc || mass == nullptr) return rc;
-    const double dx3 = (g->L[0] / g->n[0]) * (g->L[1] / g->n[1]) * (g->L[2] / g->n[2]);
-    return from_hip(launch_sum(rho, d.cells, dx3, mass, st));
+    return run_moments(g, d, prec, f, scale, rho, umean, mass, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -263,6 +263,33 @@ __device__ __forceinline__ void outflow_total(const double* red, double prev, do
     }
 }
 
+// Velocity moments of one stored block, second half: lane k < 4 of wave 0
+// adds moment k's wave sums in wave order; lane 0 writes rho = sum f du^3
+// and umean_a = sum u_a f / sum f (0 where the sum is 0), as vlasov_moments
+// defines them.
+template <int NT>
+__device__ __forceinline__ void moments_total(const double* mred, const KickArgs& a, int cell)
+{
+    const int lane = threadIdx.x;
+    const int k = lane < 4 ? lane : 0;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NT / 64; ++q) s += mred[k * (NT / 64) + q];
+    const double t0 = read_lane_f64(s, 0);
+    const double t1 = read_lane_f64(s, 1);
+    const double t2 = read_lane_f64(s, 2);
+    const double t3 = read_lane_f64(s, 3);
+    if (lane == 0) {
+        a.rho[cell] = t0 * a.du3;
+        if (a.umean != nullptr) {
+            const double inv = t0 != 0.0 ? 1.0 / t0 : 0.0;
+            a.umean[cell] = t1 * inv;
+            a.umean[a.cells + cell] = t2 * inv;
+            a.umean[2 * a.cells + cell] = t3 * inv;
+        }
+    }
+}
+
 template <int P, int NU, bool PER>
 __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __restrict__ fin,
                                                 const float* __restrict__ sin,
@@ -277,6 +304,7 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
     constexpr int NV = NU * NU * NU;
     extern __shared__ float lds[];
     __shared__ double red[3 * (NT / 64)];
+    __shared__ double mred[4 * (NT / 64)];       // wave sums of the block's moments
     __shared__ float lmax[Codec<P>::scaled ? NL : 1];   // new uz-line scales
     const int t = threadIdx.x;
     const int ncell = (int)a.cells;             // the launcher checks the range
@@ -294,7 +322,12 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
     __syncthreads();
 
     const bool ofl = a.outflow != nullptr && !PER;
+    const bool mom = a.rho != nullptr;
+    int mcell = -1;                             // cell whose moment wave sums are in mred
     for (;;) {
+        // moments of the block stored last round (published by the barrier
+        // that ended it)
+        if (mom && mcell >= 0 && t < 64) moments_total<NT>(mred, a, mcell);
         // the cell's outflow total so far, needed only after the sweeps
         double prev = 0.0;
         if (ofl && t == 0) prev = a.outflow[cell];
@@ -313,6 +346,9 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
         // by the thread that stored it, so no barrier sits in between
         T* dst = fout + (long)cell * NV;
         const int ts = fresh_tid();
+        // moments of what is stored (decoded codes for FP16/BF16), in FP64:
+        // sum f, sum u_x f, sum u_y f, sum u_z f over this thread's slots
+        double m[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < Slots::NS; ++s) {
             const int e = Slots::elem(s, ts);
@@ -322,6 +358,35 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
 #pragma unroll
             for (int u = 0; u < 4; ++u) q.v[u] = quantize<P>(src[u], inv);
             *reinterpret_cast<Pack<T, 4>*>(dst + e) = q;
+            if (mom) {
+                const float sc = Codec<P>::scaled ? lmax[e / NU] : 1.0f;
+                const int jx = e / (NU * NU), jy = (e / NU) % NU, jz = e % NU;
+                double s0 = 0.0, sz = 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double xv = (double)(Codec<P>::scaled ? Codec<P>::dec(q.v[u]) * sc
+                                                                 : Codec<P>::dec(q.v[u]));
+                    const double uz = a.umin[2] + ((double)(jz + u) + 0.5) * a.du[2];
+                    s0 += xv;
+                    sz = fma(uz, xv, sz);
+                }
+                const double ux = a.umin[0] + ((double)jx + 0.5) * a.du[0];
+                const double uy = a.umin[1] + ((double)jy + 0.5) * a.du[1];
+                m[0] += s0;
+                m[1] = fma(ux, s0, m[1]);
+                m[2] = fma(uy, s0, m[2]);
+                m[3] += sz;
+            }
+        }
+        if (mom) {
+            double w[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) w[c] = wave_sum_f64(m[c]);
+            if ((t & 63) == 0) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) mred[c * (NT / 64) + (t >> 6)] = w[c];
+            }
+            mcell = cell;
         }
         if (next >= ncell) break;
 #pragma unroll
@@ -331,6 +396,10 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
         next = uniform_sgpr(cell + (int)gridDim.x);
         if (next < ncell) R.load(fin, sin, a, next, fresh_tid());
         __syncthreads();
+    }
+    if (mom) {
+        __syncthreads();
+        if (t < 64) moments_total<NT>(mred, a, mcell);
     }
 }
 

@@ -67,6 +67,10 @@ struct KickArgs {
     double du3;
     long cells;
     int nu[3];
+    double* rho;     // moments of the stored result per cell, or nullptr
+    double* umean;   // [3][cells], or nullptr
+    double umin[3];  // -umax (cell centres for the moments)
+    double du[3];
 };
 bool kick_supported(const int nu[3], size_t lds_limit);
 // shifts: [cells][3] table written by the kick's own pre-pass on the same

@@ -77,6 +77,8 @@ def _load():
     L.vlasov_step_workspace_bytes.argtypes = [G, I]
     L.vlasov_step.restype = I
     L.vlasov_step.argtypes = [G, I, I, P, P, P, P, P, P, D, D, P, S, P, P]
+    L.vlasov_step_moments.restype = I
+    L.vlasov_step_moments.argtypes = [G, I, I, P, P, P, P, P, P, D, D, P, S, P, P, P, P]
     L.vlasov_moments.restype = I
     L.vlasov_moments.argtypes = [G, I, P, P, P, P, P, P]
     L.vlasov_sum_f64.restype = I
@@ -204,6 +206,15 @@ def vlasov_step(grid, prec, vbc, f_in, scale_in, f_out, scale_out, g_n, g_np1, d
                             _ptr(f_out), _ptr(scale_out), _ptr(g_n), _ptr(g_np1), float(dt),
                             float(a2inv), _ptr(work), int(work_bytes), _ptr(outflow),
                             _stream(stream)), "vlasov_step")
+
+
+def vlasov_step_moments(grid, prec, vbc, f_in, scale_in, f_out, scale_out, g_n, g_np1, dt,
+                        a2inv, work, work_bytes, outflow, rho, umean, stream=None):
+    _check(_lib.vlasov_step_moments(ctypes.byref(grid), prec, vbc, _ptr(f_in), _ptr(scale_in),
+                                    _ptr(f_out), _ptr(scale_out), _ptr(g_n), _ptr(g_np1),
+                                    float(dt), float(a2inv), _ptr(work), int(work_bytes),
+                                    _ptr(outflow), _ptr(rho), _ptr(umean), _stream(stream)),
+           "vlasov_step_moments")
 
 
 def vlasov_moments(grid, prec, f, scale, rho, umean, mass, stream=None):
