@@ -475,6 +475,70 @@ int vlasov_step_moments(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, 
                      outflow, rho, umean, stream);
 }
 
+size_t vlasov_steps_workspace_bytes(const vlasov_grid* grid, vlasov_prec prec)
+{
+    Dims d;
+    if (!dims_of(grid, d) || !prec_ok(prec)) return 0;
+    return 2 * shift_table_offset(d, prec) + align_up((size_t)(3 * d.cells) * sizeof(KickShift));
+}
+
+int vlasov_steps(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
+                 const float* sin, void* fout, float* sout, const float* fields, int nsteps,
+                 double dt, const double* a2inv, void* work, size_t work_bytes, double* outflow,
+                 void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (vbc != VLASOV_VBC_OUTFLOW && vbc != VLASOV_VBC_PERIODIC) return VLASOV_ERR_PREC;
+    if (fields == nullptr) return VLASOV_ERR_NULL;
+    if (nsteps < 1) return VLASOV_ERR_SHAPE;
+    int rc = check_io(d, prec, fin, sin, fout, sout);
+    if (rc) return rc;
+    if (!isfinite(dt)) return VLASOV_ERR_NONFINITE;
+    for (int k = 0; k < nsteps; ++k) {
+        const double a = a2inv != nullptr ? a2inv[k] : 1.0;
+        if (!isfinite(a) || !isfinite(dt * a)) return VLASOV_ERR_NONFINITE;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (d.nu[a] > kMaxShiftTable) return VLASOV_ERR_SHAPE;
+    const size_t need = vlasov_steps_workspace_bytes(g, prec);
+    if (work == nullptr || work_bytes < need) return VLASOV_ERR_WORKSPACE;
+    const size_t fb = (size_t)d.total * elem_bytes(prec);
+    const size_t sb = prec == VLASOV_F32 ? 0 : (size_t)(d.total / d.nu[2]) * sizeof(float);
+    const size_t gb = (size_t)(nsteps + 1) * 3 * d.cells * sizeof(float);
+    if (overlap(work, need, fin, fb) || overlap(work, need, fout, fb) ||
+        overlap(work, need, sin, sb) || overlap(work, need, sout, sb) ||
+        overlap(work, need, fields, gb) || overlap(fout, fb, fields, gb))
+        return VLASOV_ERR_ALIAS;
+    // two intermediate copies: the drifts ping-pong between f_out and the
+    // first; a kick that cannot run fused uses the second as its middle stage
+    const size_t one = shift_table_offset(d, prec);
+    void* w1 = work;
+    float* s1 = prec == VLASOV_F32 ? nullptr : (float*)((char*)w1 + align_up(fb));
+    void* w2 = (char*)work + one;
+    float* s2 = prec == VLASOV_F32 ? nullptr : (float*)((char*)w2 + align_up(fb));
+    KickShift* tab = (KickShift*)((char*)work + 2 * one);
+    hipStream_t st = (hipStream_t)stream;
+    const size_t gstride = (size_t)3 * d.cells;
+    // K(dt/2; g_0), then per step: z, y, x over dt a^-2 and the merged kick
+    // K(dt; g_{k+1}) (K(dt/2; g_n) after the last step)
+    if ((rc = run_kick(g, d, prec, vbc, fin, sin, fout, sout, w1, s1, fields, 0.5 * dt, outflow,
+                       tab, st)))
+        return rc;
+    for (int k = 0; k < nsteps; ++k) {
+        const double dta = dt * (a2inv != nullptr ? a2inv[k] : 1.0);
+        if ((rc = run_position(g, d, 2, prec, fout, sout, w1, s1, dta, st))) return rc;
+        if ((rc = run_position(g, d, 1, prec, w1, s1, fout, sout, dta, st))) return rc;
+        if ((rc = run_position(g, d, 0, prec, fout, sout, w1, s1, dta, st))) return rc;
+        const double h = k + 1 < nsteps ? dt : 0.5 * dt;
+        if ((rc = run_kick(g, d, prec, vbc, w1, s1, fout, sout, w2, s2,
+                           fields + (size_t)(k + 1) * gstride, h, outflow, tab, st)))
+            return rc;
+    }
+    return VLASOV_OK;
+}
+
 int vlasov_kick(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
                 const float* sin, void* fout, float* sout, const float* field, double dt,
                 void* work, size_t work_bytes, double* outflow, void* stream)

@@ -77,6 +77,10 @@ def _load():
     L.vlasov_step_workspace_bytes.argtypes = [G, I]
     L.vlasov_step.restype = I
     L.vlasov_step.argtypes = [G, I, I, P, P, P, P, P, P, D, D, P, S, P, P]
+    L.vlasov_steps_workspace_bytes.restype = S
+    L.vlasov_steps_workspace_bytes.argtypes = [G, I]
+    L.vlasov_steps.restype = I
+    L.vlasov_steps.argtypes = [G, I, I, P, P, P, P, P, I, D, P, P, S, P, P]
     L.vlasov_step_moments.restype = I
     L.vlasov_step_moments.argtypes = [G, I, I, P, P, P, P, P, P, D, D, P, S, P, P, P, P]
     L.vlasov_moments.restype = I
@@ -206,6 +210,23 @@ def vlasov_step(grid, prec, vbc, f_in, scale_in, f_out, scale_out, g_n, g_np1, d
                             _ptr(f_out), _ptr(scale_out), _ptr(g_n), _ptr(g_np1), float(dt),
                             float(a2inv), _ptr(work), int(work_bytes), _ptr(outflow),
                             _stream(stream)), "vlasov_step")
+
+
+def vlasov_steps_workspace_bytes(grid, prec) -> int:
+    return _lib.vlasov_steps_workspace_bytes(ctypes.byref(grid), prec)
+
+
+def vlasov_steps(grid, prec, vbc, f_in, scale_in, f_out, scale_out, fields, nsteps, dt, a2inv,
+                 work, work_bytes, outflow=None, stream=None):
+    """a2inv: None or a sequence of nsteps host values."""
+    a2 = None
+    if a2inv is not None:
+        a2 = (ctypes.c_double * int(nsteps))(*[float(v) for v in a2inv])
+    _check(_lib.vlasov_steps(ctypes.byref(grid), prec, vbc, _ptr(f_in), _ptr(scale_in),
+                             _ptr(f_out), _ptr(scale_out), _ptr(fields), int(nsteps), float(dt),
+                             ctypes.cast(a2, ctypes.c_void_p) if a2 is not None else None,
+                             _ptr(work), int(work_bytes), _ptr(outflow), _stream(stream)),
+           "vlasov_steps")
 
 
 def vlasov_step_moments(grid, prec, vbc, f_in, scale_in, f_out, scale_out, g_n, g_np1, dt,
