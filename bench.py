@@ -187,6 +187,73 @@ def timed_run(V, torch, inputs, w, grid, prec, K, W, dev, stream):
     return {"total_ms": total_ms, "step_ms": step_ms, "per": per, "t_wall": t_wall}
 
 
+def companion_run(V, torch, inputs, w, grid, prec, K, dev, stream):
+    """Two other forms of the same work, for comparison (not the headline):
+    K steps through vlasov_steps, whose half kicks between steps run as one
+    kick (it rounds differently from K single steps), and one step with the
+    moments of its result fused into the last kick, against a step followed by
+    a moments pass."""
+    f0 = inputs.initial_f32_device(w, dev)
+    state = V.encode(grid, prec, f0)
+    if prec != V.F32:
+        del f0
+    pot = inputs.potential(w)
+    fields = torch.stack([torch.from_numpy(inputs.accel_field(w, pot, k * w.dt))
+                          for k in range(K + 1)]).to(dev)
+    out = V.empty_state(grid, prec, dev)
+    nb = V.vlasov_steps_workspace_bytes(grid, prec)
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
+    rho = torch.empty(tuple(w.n), dtype=torch.float64, device=dev)
+    um = torch.empty((3,) + tuple(w.n), dtype=torch.float64, device=dev)
+
+    def timed(fn, reps=2):
+        fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    def merged():
+        V.vlasov_steps(grid, prec, V.VBC_OUTFLOW, state.f, state.scale, out.f, out.scale, fields,
+                       K, w.dt, None, work, nb, None, stream)
+
+    def step():
+        V.vlasov_step(grid, prec, V.VBC_OUTFLOW, state.f, state.scale, out.f, out.scale,
+                      fields[0], fields[1], w.dt, 1.0, work, nb, None, stream)
+
+    def step_mom():
+        V.vlasov_step_moments(grid, prec, V.VBC_OUTFLOW, state.f, state.scale, out.f,
+                              out.scale, fields[0], fields[1], w.dt, 1.0, work, nb, None, rho,
+                              um, stream)
+
+    def mom():
+        V.vlasov_moments(grid, prec, out.f, out.scale, rho, um, None, stream)
+
+    ms_merged = timed(merged, reps=1) / K
+    ms_step, ms_step_mom, ms_mom = timed(step), timed(step_mom), timed(mom)
+    del state, out, work, fields, rho, um
+    torch.cuda.empty_cache()
+    return {
+        "merged_half_kicks": {
+            "value": w.cells / (ms_merged * 1e-3),
+            "unit": "cell-updates/s",
+            "ms_per_step": ms_merged,
+            "steps": K,
+            "speedup_vs_single_step_calls": ms_step / ms_merged,
+            "form": "vlasov_steps: the two half kicks between steps run as one kick "
+                    "(4 passes per step instead of 5); not Eq. (5) step by step",
+        },
+        "fused_moments": {
+            "step_ms": ms_step,
+            "step_with_fused_moments_ms": ms_step_mom,
+            "separate_moments_pass_ms": ms_mom,
+        },
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +264,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16", action="store_true",
                     help="skip the FP16-storage companion run of an FP32 bench")
+    ap.add_argument("--no-companions", action="store_true",
+                    help="skip the merged-kick and fused-moments companion timings")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the sweeps shard along space across GPUs "
@@ -317,6 +386,9 @@ def main():
             "hbm_tbps_algorithmic": bytes16 / (ms16 * 1e-3) / 1e12,
         }
         _log("bench: fp16 per-kernel ms " + json.dumps({k: round(v, 3) for k, v in avg16.items()}))
+    if not args.no_companions:
+        _log("bench: companion timings (merged half kicks, fused moments)")
+        res["companions"] = companion_run(V, torch, inputs, w, grid, prec, K, dev, stream)
     if not args.no_cpu_baseline:
         _log("bench: timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline()
