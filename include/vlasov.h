@@ -223,6 +223,53 @@ int vlasov_steps(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, cons
                  int nsteps, double dt, const double* a2inv, void* work, size_t work_bytes,
                  double* outflow, void* stream);
 
+/* Bytes of workspace vlasov_field needs (twiddle tables and FP64 complex
+ * spectra, 256-byte aligned). */
+size_t vlasov_field_workspace_bytes(const vlasov_grid* grid);
+
+/*
+ * The acceleration field of a density on the periodic spatial mesh: the
+ * Poisson equation (Eq. 2), nabla^2 phi = coupling (rho - mean rho), solved
+ * by the discrete Fourier transform (the convolution method of the paper's
+ * mesh part, section 3), and g = -grad phi (the speed of Eq. 4):
+ *   phi_k = -coupling rho_k / |k|^2 (mean removed), g_a,k = -i k_a phi_k,
+ *   k_a = 2 pi m_a / L_a with m_a the signed index; k_a = 0 on the Nyquist
+ *   plane of an even axis for the derivative.
+ * FP64 throughout (separable DFTs, one pass per axis), g stored as FP32.
+ *   rho      : FP64 device [nx][ny][nz] (e.g. from vlasov_moments)
+ *   coupling : 4 pi G a(t)^2
+ *   field    : FP32 device [3][nx][ny][nz], the layout vlasov_step takes
+ *   work     : device workspace of at least vlasov_field_workspace_bytes
+ * Errors: VLASOV_ERR_NULL, VLASOV_ERR_SHAPE (bad grid, L <= 0),
+ * VLASOV_ERR_NONFINITE, VLASOV_ERR_WORKSPACE, VLASOV_ERR_ALIAS.
+ */
+int vlasov_field(const vlasov_grid* grid, const double* rho, double coupling, float* field,
+                 void* work, size_t work_bytes, void* stream);
+
+/* Bytes of workspace vlasov_step_sc needs: vlasov_step's, 256-byte aligned,
+ * followed by vlasov_field's. */
+size_t vlasov_step_sc_workspace_bytes(const vlasov_grid* grid, vlasov_prec prec);
+
+/*
+ * One self-consistent step of the Vlasov-Poisson system (Eqs. 1, 2, 5):
+ * half kicks ux, uy, uz with the field g_n at t^n, drifts z, y, x, then the
+ * density of the drifted f (the kicks move f along u only, so it is the
+ * density at t^{n+1}), its field by vlasov_field with `coupling`
+ * (4 pi G a(t^{n+1})^2), and the half kicks with that field.  The density is
+ * that of f alone: the CDM part of the paper's mesh density is not modelled.
+ *   g_n     : FP32 device [3][nx][ny][nz], field at t^n (vlasov_field of the
+ *             density of f^n, or the previous step's g_np1)
+ *   g_np1   : FP32 device [3][nx][ny][nz], OUT: field at t^{n+1}
+ *   rho_np1 : FP64 device [nx][ny][nz], OUT: density of f^{n+1}
+ *   work    : device workspace of at least vlasov_step_sc_workspace_bytes
+ * Other arguments and errors as vlasov_step and vlasov_field; g_np1 and
+ * rho_np1 must not overlap each other, g_n, f_in, f_out or work.
+ */
+int vlasov_step_sc(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, const void* f_in,
+                   const float* scale_in, void* f_out, float* scale_out, const float* g_n,
+                   float* g_np1, double* rho_np1, double coupling, double dt, double a2inv,
+                   void* work, size_t work_bytes, double* outflow, void* stream);
+
 /*
  * Velocity moments per spatial cell (section 5.1.3), accumulated in FP64:
  *   rho[c]      = sum_u f du^3

@@ -244,6 +244,51 @@ def steps_merged(grid: Grid, fields, f, dt: float, a2inv=None, vbc: int = 0, out
     return f
 
 
+def field_from_density(grid: Grid, rho, coupling: float):
+    """Eq. (2) on the periodic box, nabla^2 phi = coupling (rho - mean rho),
+    solved in Fourier space (the convolution method of section 3, numpy's FFT
+    as the transform): phi_k = -coupling rho_k / |k|^2 with phi_0 = 0, and
+    g = -grad phi, g_a,k = -i k_a phi_k with k_a = 2 pi m_a / L_a (m_a the
+    signed index) and k_a = 0 on the Nyquist plane of an even axis.
+    Returns g [3][nx][ny][nz] in FP64."""
+    rho = np.asarray(rho, dtype=np.float64).reshape(tuple(grid.n))
+    R = np.fft.fftn(rho)
+    ks = []
+    for a in range(3):
+        n = grid.n[a]
+        m = np.fft.fftfreq(n, d=1.0 / n)                 # signed indices, Nyquist -n/2
+        ks.append(2.0 * np.pi * m / grid.L[a])
+    KX, KY, KZ = np.meshgrid(ks[0], ks[1], ks[2], indexing="ij")
+    K2 = KX ** 2 + KY ** 2 + KZ ** 2
+    phi = np.zeros_like(R)
+    nz = K2 != 0.0
+    phi[nz] = -coupling * R[nz] / K2[nz]
+    out = np.empty((3,) + tuple(grid.n))
+    for a, K in enumerate((KX, KY, KZ)):
+        Ka = K.copy()
+        if grid.n[a] % 2 == 0:
+            sl = [slice(None)] * 3
+            sl[a] = grid.n[a] // 2
+            Ka[tuple(sl)] = 0.0
+        out[a] = np.real(np.fft.ifftn(-1j * Ka * phi))
+    return out
+
+
+def step_sc(grid: Grid, f, g_n, coupling: float, dt: float, a2inv: float = 1.0, vbc: int = 0,
+            outflow=None):
+    """One self-consistent step: kick(g_n) over dt/2, drifts z, y, x, the field
+    of the drifted f's density (Eq. 2, field_from_density), kick over dt/2
+    with it.  Returns (f^{n+1}, g^{n+1} rounded to FP32 as the sweeps read
+    it, rho^{n+1})."""
+    f = kick(grid, f, g_n, 0.5 * dt, vbc, outflow)
+    for axis in (2, 1, 0):
+        f = advect_position(grid, axis, f, dt * a2inv)
+    rho, _, _ = moments(grid, f)
+    g = field_from_density(grid, rho, coupling).astype(np.float32)
+    f = kick(grid, f, g, 0.5 * dt, vbc, outflow)
+    return f, g, rho
+
+
 def moments(grid: Grid, f):
     """Returns (rho [cells], umean [3, cells], mass)."""
     f = _f64(f)

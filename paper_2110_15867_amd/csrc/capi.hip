@@ -598,6 +598,117 @@ int vlasov_moments(const vlasov_grid* g, vlasov_prec prec, const void* f, const 
     return run_moments(g, d, prec, f, scale, rho, umean, mass, (hipStream_t)stream);
 }
 
+size_t vlasov_step_sc_workspace_bytes(const vlasov_grid* grid, vlasov_prec prec)
+{
+    Dims d;
+    if (!dims_of(grid, d) || !prec_ok(prec)) return 0;
+    const int n[3] = {(int)d.n[0], (int)d.n[1], (int)d.n[2]};
+    return align_up(vlasov_step_workspace_bytes(grid, prec)) + field_workspace_bytes(n);
+}
+
+int vlasov_step_sc(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, const void* fin,
+                   const float* sin, void* fout, float* sout, const float* g_n, float* g_np1,
+                   double* rho_np1, double coupling, double dt, double a2inv, void* work,
+                   size_t work_bytes, double* outflow, void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (vbc != VLASOV_VBC_OUTFLOW && vbc != VLASOV_VBC_PERIODIC) return VLASOV_ERR_PREC;
+    if (g_n == nullptr || g_np1 == nullptr || rho_np1 == nullptr) return VLASOV_ERR_NULL;
+    int rc = check_io(d, prec, fin, sin, fout, sout);
+    if (rc) return rc;
+    if (!isfinite(dt) || !isfinite(a2inv) || !isfinite(dt * a2inv) || !isfinite(coupling))
+        return VLASOV_ERR_NONFINITE;
+    for (int a = 0; a < 3; ++a) {
+        if (d.nu[a] > kMaxShiftTable) return VLASOV_ERR_SHAPE;
+        if (!(g->L[a] > 0.0) || !isfinite(g->L[a])) return VLASOV_ERR_SHAPE;
+    }
+    const size_t need = vlasov_step_sc_workspace_bytes(g, prec);
+    if (work == nullptr || work_bytes < need) return VLASOV_ERR_WORKSPACE;
+    const size_t fb = (size_t)d.total * elem_bytes(prec);
+    const size_t sb = prec == VLASOV_F32 ? 0 : (size_t)(d.total / d.nu[2]) * sizeof(float);
+    const size_t gb = 3 * (size_t)d.cells * sizeof(float);
+    const size_t rb = (size_t)d.cells * sizeof(double);
+    if (overlap(work, need, fin, fb) || overlap(work, need, fout, fb) ||
+        overlap(work, need, sin, sb) || overlap(work, need, sout, sb) ||
+        overlap(work, need, g_n, gb) || overlap(work, need, g_np1, gb) ||
+        overlap(work, need, rho_np1, rb) || overlap(fout, fb, g_n, gb) ||
+        overlap(fout, fb, g_np1, gb) || overlap(fout, fb, rho_np1, rb) ||
+        overlap(g_np1, gb, g_n, gb) || overlap(g_np1, gb, rho_np1, rb) ||
+        overlap(fin, fb, g_np1, gb) || overlap(fin, fb, rho_np1, rb))
+        return VLASOV_ERR_ALIAS;
+    hipStream_t st = (hipStream_t)stream;
+    void* wf = work;
+    float* ws = prec == VLASOV_F32 ? nullptr : (float*)((char*)work + align_up(fb));
+    KickShift* tab = (KickShift*)((char*)work + shift_table_offset(d, prec));
+    void* fwork = (char*)work + align_up(vlasov_step_workspace_bytes(g, prec));
+    const double h = 0.5 * dt;
+    const double dta = dt * a2inv;
+    // kick(g_n) -> z -> y -> x; the kicks leave the density alone, so the
+    // drifted f has the density of f^{n+1}: its field drives the last kick
+    if ((rc = run_kick(g, d, prec, vbc, fin, sin, fout, sout, wf, ws, g_n, h, outflow, tab, st)))
+        return rc;
+    if ((rc = run_position(g, d, 2, prec, fout, sout, wf, ws, dta, st))) return rc;
+    if ((rc = run_position(g, d, 1, prec, wf, ws, fout, sout, dta, st))) return rc;
+    if ((rc = run_position(g, d, 0, prec, fout, sout, wf, ws, dta, st))) return rc;
+    if ((rc = run_moments(g, d, prec, wf, ws, rho_np1, nullptr, nullptr, st))) return rc;
+    FieldArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    for (int k = 0; k < 3; ++k) {
+        fa.n[k] = (int)d.n[k];
+        fa.L[k] = g->L[k];
+    }
+    fa.coupling = coupling;
+    fa.cells = d.cells;
+    if ((rc = from_hip(launch_field(rho_np1, g_np1, fa, fwork, st)))) return rc;
+    if ((rc = run_kick(g, d, prec, vbc, wf, ws, fout, sout, nullptr, nullptr, g_np1, h, outflow,
+                       tab, st)) == VLASOV_ERR_WORKSPACE) {
+        if ((rc = run_velocity(g, d, 0, prec, vbc, wf, ws, fout, sout, g_np1, h, outflow, st)))
+            return rc;
+        if ((rc = run_velocity(g, d, 1, prec, vbc, fout, sout, wf, ws, g_np1, h, outflow, st)))
+            return rc;
+        rc = run_velocity(g, d, 2, prec, vbc, wf, ws, fout, sout, g_np1, h, outflow, st);
+    }
+    return rc;
+}
+
+size_t vlasov_field_workspace_bytes(const vlasov_grid* grid)
+{
+    Dims d;
+    if (!dims_of(grid, d)) return 0;
+    const int n[3] = {(int)d.n[0], (int)d.n[1], (int)d.n[2]};
+    return field_workspace_bytes(n);
+}
+
+int vlasov_field(const vlasov_grid* g, const double* rho, double coupling, float* field,
+                 void* work, size_t work_bytes, void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (rho == nullptr || field == nullptr) return VLASOV_ERR_NULL;
+    if (!isfinite(coupling)) return VLASOV_ERR_NONFINITE;
+    for (int a = 0; a < 3; ++a)
+        if (!(g->L[a] > 0.0) || !isfinite(g->L[a])) return VLASOV_ERR_SHAPE;
+    const size_t need = vlasov_field_workspace_bytes(g);
+    if (work == nullptr || work_bytes < need) return VLASOV_ERR_WORKSPACE;
+    const size_t nb = (size_t)d.cells * sizeof(double);
+    const size_t fb = 3 * (size_t)d.cells * sizeof(float);
+    if (overlap(work, need, rho, nb) || overlap(work, need, field, fb) ||
+        overlap(rho, nb, field, fb))
+        return VLASOV_ERR_ALIAS;
+    FieldArgs a;
+    memset(&a, 0, sizeof(a));
+    for (int k = 0; k < 3; ++k) {
+        a.n[k] = (int)d.n[k];
+        a.L[k] = g->L[k];
+    }
+    a.coupling = coupling;
+    a.cells = d.cells;
+    return from_hip(launch_field(rho, field, a, work, (hipStream_t)stream));
+}
+
 // ---------------------------------------------------------------------------
 // Tangents and adjoints (FP32 storage)
 // ---------------------------------------------------------------------------

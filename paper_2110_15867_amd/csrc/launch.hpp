@@ -92,6 +92,25 @@ struct MomArgs {
 hipError_t launch_moments(int prec, const void* f, const float* scale, const MomArgs& a,
                           hipStream_t st);
 hipError_t launch_sum(const double* x, long n, double scale, double* out, hipStream_t st);
+
+// Field of a density on the periodic mesh (Eq. 2), FP64 DFTs.
+struct FieldArgs {
+    int n[3];
+    double L[3];
+    double coupling; // 4 pi G a^2
+    long cells;
+};
+inline size_t field_align(size_t b) { return (b + 255) & ~(size_t)255; }
+// workspace: three twiddle tables, two complex [cells] buffers, three more
+inline size_t field_workspace_bytes(const int n[3])
+{
+    const size_t cells = (size_t)n[0] * n[1] * n[2];
+    size_t b = 0;
+    for (int d = 0; d < 3; ++d) b += field_align((size_t)n[d] * 16);
+    return b + 2 * field_align(cells * 16) + field_align(3 * cells * 16);
+}
+hipError_t launch_field(const double* rho, float* g, const FieldArgs& a, void* work,
+                        hipStream_t st);
 hipError_t launch_moments_adj(const MomArgs& a, const double* lam_rho, const double* lam_umean,
                               float* lam_f, hipStream_t st);
 

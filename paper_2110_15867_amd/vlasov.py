@@ -77,6 +77,14 @@ def _load():
     L.vlasov_step_workspace_bytes.argtypes = [G, I]
     L.vlasov_step.restype = I
     L.vlasov_step.argtypes = [G, I, I, P, P, P, P, P, P, D, D, P, S, P, P]
+    L.vlasov_step_sc_workspace_bytes.restype = S
+    L.vlasov_step_sc_workspace_bytes.argtypes = [G, I]
+    L.vlasov_step_sc.restype = I
+    L.vlasov_step_sc.argtypes = [G, I, I, P, P, P, P, P, P, P, D, D, D, P, S, P, P]
+    L.vlasov_field_workspace_bytes.restype = S
+    L.vlasov_field_workspace_bytes.argtypes = [G]
+    L.vlasov_field.restype = I
+    L.vlasov_field.argtypes = [G, P, D, P, P, S, P]
     L.vlasov_steps_workspace_bytes.restype = S
     L.vlasov_steps_workspace_bytes.argtypes = [G, I]
     L.vlasov_steps.restype = I
@@ -210,6 +218,38 @@ def vlasov_step(grid, prec, vbc, f_in, scale_in, f_out, scale_out, g_n, g_np1, d
                             _ptr(f_out), _ptr(scale_out), _ptr(g_n), _ptr(g_np1), float(dt),
                             float(a2inv), _ptr(work), int(work_bytes), _ptr(outflow),
                             _stream(stream)), "vlasov_step")
+
+
+def vlasov_step_sc_workspace_bytes(grid, prec) -> int:
+    return _lib.vlasov_step_sc_workspace_bytes(ctypes.byref(grid), prec)
+
+
+def vlasov_step_sc(grid, prec, vbc, f_in, scale_in, f_out, scale_out, g_n, g_np1, rho_np1,
+                   coupling, dt, a2inv, work, work_bytes, outflow=None, stream=None):
+    _check(_lib.vlasov_step_sc(ctypes.byref(grid), prec, vbc, _ptr(f_in), _ptr(scale_in),
+                               _ptr(f_out), _ptr(scale_out), _ptr(g_n), _ptr(g_np1),
+                               _ptr(rho_np1), float(coupling), float(dt), float(a2inv),
+                               _ptr(work), int(work_bytes), _ptr(outflow), _stream(stream)),
+           "vlasov_step_sc")
+
+
+def vlasov_field_workspace_bytes(grid) -> int:
+    return _lib.vlasov_field_workspace_bytes(ctypes.byref(grid))
+
+
+def vlasov_field(grid, rho, coupling, field, work, work_bytes, stream=None):
+    _check(_lib.vlasov_field(ctypes.byref(grid), _ptr(rho), float(coupling), _ptr(field),
+                             _ptr(work), int(work_bytes), _stream(stream)), "vlasov_field")
+
+
+def field(grid, rho, coupling, stream=None):
+    """Acceleration field [3][nx][ny][nz] (FP32) of an FP64 density."""
+    n = tuple(grid.n)
+    out = torch.empty((3,) + n, dtype=torch.float32, device=rho.device)
+    nb = vlasov_field_workspace_bytes(grid)
+    work = torch.empty(nb, dtype=torch.uint8, device=rho.device)
+    vlasov_field(grid, rho, coupling, out, work, nb, stream)
+    return out
 
 
 def vlasov_steps_workspace_bytes(grid, prec) -> int:
