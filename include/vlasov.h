@@ -185,7 +185,7 @@ int vlasov_step(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, const
  * summation order differs from vlasov_moments', so the two agree to FP64
  * rounding, not to the bit.  f_out is the bits vlasov_step writes.
  * Errors: as vlasov_step; VLASOV_ERR_NULL for a NULL rho; VLASOV_ERR_ALIAS
- * when rho or umean overlap each other, f_out or work.
+ * when rho or umean overlap each other, f_in, f_out or work.
  */
 int vlasov_step_moments(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc,
                         const void* f_in, const float* scale_in, void* f_out, float* scale_out,

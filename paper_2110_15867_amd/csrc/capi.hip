@@ -469,6 +469,7 @@ int vlasov_step_moments(const vlasov_grid* g, vlasov_prec prec, vlasov_vbc vbc, 
     if (umean != nullptr && overlap(rho, nb, umean, 3 * nb)) return VLASOV_ERR_ALIAS;
     const size_t fb = (size_t)d.total * elem_bytes(prec);
     if (overlap(fout, fb, rho, nb) || overlap(fout, fb, umean, 3 * nb) ||
+        overlap(fin, fb, rho, nb) || overlap(fin, fb, umean, 3 * nb) ||
         overlap(work, work_bytes, rho, nb) || overlap(work, work_bytes, umean, 3 * nb))
         return VLASOV_ERR_ALIAS;
     return step_impl(g, prec, vbc, fin, sin, fout, sout, g_n, g_np1, dt, a2inv, work, work_bytes,
