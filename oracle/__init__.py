@@ -95,6 +95,8 @@ def lib():
         L.vor_moments.restype = ctypes.c_int
         L.vor_moments.argtypes = [ctypes.POINTER(Grid), c_double_p, c_double_p, c_double_p,
                                   c_double_p]
+        L.vor_dispersion.restype = ctypes.c_int
+        L.vor_dispersion.argtypes = [ctypes.POINTER(Grid), c_double_p, c_double_p]
         G = ctypes.POINTER(Grid)
         D, I, Lg = ctypes.c_double, ctypes.c_int, ctypes.c_long
         L.vor_sweep_line_jacobian.restype = None
@@ -299,6 +301,19 @@ def moments(grid: Grid, f):
     _check(lib().vor_moments(ctypes.byref(grid), _dp(f), _dp(rho), _dp(um), ctypes.byref(mass)),
            "moments")
     return rho.reshape(tuple(grid.n)), um.reshape((3,) + tuple(grid.n)), mass.value
+
+
+DISPERSION_COMPONENTS = ((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))
+
+
+def dispersion(grid: Grid, f):
+    """Velocity dispersion tensor [6, cells] (xx, xy, xz, yy, yz, zz): the
+    density-weighted covariance of u in each spatial cell (section 5.1.3)."""
+    f = _f64(f)
+    nx = grid.n[0] * grid.n[1] * grid.n[2]
+    sig = np.empty(6 * nx)
+    _check(lib().vor_dispersion(ctypes.byref(grid), _dp(f), _dp(sig)), "dispersion")
+    return sig.reshape((6,) + tuple(grid.n))
 
 
 # --- derivatives (frozen limiter selections) ----------------------------------------

@@ -20,8 +20,8 @@
  *     (the exact integral of the reconstruction over the upwind departure
  *     interval), limited by the Suresh-Huynh monotonicity-preserving bounds
  *     and by a positivity clamp, evaluated once per step (single stage);
- *   - velocity moments per spatial cell (section 5.1.3): density and mean
- *     velocity.
+ *   - velocity moments per spatial cell (section 5.1.3): density, mean
+ *     velocity and the velocity dispersion tensor.
  * The paper prints no formula for the scheme; the readings taken here (alpha,
  * epsilon, the positivity form, the velocity boundary, the time level of the
  * field in the second half kick) are listed with the build's design notes.
@@ -398,6 +398,53 @@ int vor_moments(const vor_grid* g, const double* f, double* rho, double* umean, 
         double m = 0.0;
         for (c = 0; c < Nx; ++c) m += rho[c];
         *mass = m * dx3;
+    }
+    return 0;
+}
+
+/* Velocity dispersion tensor per spatial cell (section 5.1.3 lists it with
+ * the density and mean velocity among the moments taken without data
+ * exchange; the paper gives no formula).  Read as the density-weighted
+ * covariance of u over the cell's velocity block:
+ *   sigma_lm(x) = sum_u (u_l - umean_l)(u_m - umean_m) f / sum_u f,
+ * 0 where sum_u f = 0.  Written as its definition: a first pass for the mean,
+ * a second for the central products.  Layout [6][cells], components in the
+ * order xx, xy, xz, yy, yz, zz. */
+int vor_dispersion(const vor_grid* g, const double* f, double* sigma)
+{
+    long Nx, Nu, c;
+    int rc = vor_check_grid(g);
+    if (rc) return rc;
+    Nx = ncell_x(g);
+    Nu = ncell_u(g);
+    double du[3];
+    for (int a = 0; a < 3; ++a) du[a] = 2.0 * g->umax[a] / g->nu[a];
+    static const int comp[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    #pragma omp parallel for schedule(static)
+    for (c = 0; c < Nx; ++c) {
+        const double* blk = f + c * Nu;
+        double m0 = 0.0, mean[3] = {0.0, 0.0, 0.0};
+        for (long ju = 0; ju < Nu; ++ju) {
+            double u[3];
+            u[0] = -g->umax[0] + (ju / ((long)g->nu[1] * g->nu[2]) + 0.5) * du[0];
+            u[1] = -g->umax[1] + ((ju / g->nu[2]) % g->nu[1] + 0.5) * du[1];
+            u[2] = -g->umax[2] + (ju % g->nu[2] + 0.5) * du[2];
+            m0 += blk[ju];
+            for (int a = 0; a < 3; ++a) mean[a] += u[a] * blk[ju];
+        }
+        double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (m0 != 0.0) {
+            for (int a = 0; a < 3; ++a) mean[a] /= m0;
+            for (long ju = 0; ju < Nu; ++ju) {
+                double d[3];
+                d[0] = -g->umax[0] + (ju / ((long)g->nu[1] * g->nu[2]) + 0.5) * du[0] - mean[0];
+                d[1] = -g->umax[1] + ((ju / g->nu[2]) % g->nu[1] + 0.5) * du[1] - mean[1];
+                d[2] = -g->umax[2] + (ju % g->nu[2] + 0.5) * du[2] - mean[2];
+                for (int k = 0; k < 6; ++k) s[k] += d[comp[k][0]] * d[comp[k][1]] * blk[ju];
+            }
+            for (int k = 0; k < 6; ++k) s[k] /= m0;
+        }
+        for (int k = 0; k < 6; ++k) sigma[(long)k * Nx + c] = s[k];
     }
     return 0;
 }

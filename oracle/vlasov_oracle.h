@@ -39,6 +39,7 @@ int vor_advect_velocity(const vor_grid* g, int a, int vbc, const double* fin, do
 int vor_step(const vor_grid* g, int vbc, const double* fin, double* fout, double* work,
              const float* g_n, const float* g_np1, double dt, double a2inv, double* outflow);
 int vor_moments(const vor_grid* g, const double* f, double* rho, double* umean, double* mass);
+int vor_dispersion(const vor_grid* g, const double* f, double* sigma);
 
 /* derivatives (vlasov_oracle_adj.c) */
 void vor_sweep_line_jacobian(const double* f, long M, double s, int periodic, int limiter,
