@@ -232,9 +232,15 @@ def companion_run(V, torch, inputs, w, grid, prec, K, dev, stream):
     def mom():
         V.vlasov_moments(grid, prec, out.f, out.scale, rho, um, None, stream)
 
+    sig = torch.empty((6,) + tuple(w.n), dtype=torch.float64, device=dev)
+
+    def disp():
+        V.vlasov_dispersion(grid, prec, out.f, out.scale, rho, um, sig, stream)
+
     ms_merged = timed(merged, reps=1) / K
     ms_step, ms_step_mom, ms_mom = timed(step), timed(step_mom), timed(mom)
-    del state, out, work, fields, rho, um
+    ms_disp = timed(disp)
+    del state, out, work, fields, rho, um, sig
     torch.cuda.empty_cache()
     return {
         "merged_half_kicks": {
@@ -250,6 +256,9 @@ def companion_run(V, torch, inputs, w, grid, prec, K, dev, stream):
             "step_ms": ms_step,
             "step_with_fused_moments_ms": ms_step_mom,
             "separate_moments_pass_ms": ms_mom,
+            "dispersion_tensor_pass_ms": ms_disp,
+            "dispersion_tensor_pass_GBps": (V.vlasov_f_bytes(grid, prec)
+                                            + V.vlasov_scale_bytes(grid, prec)) / (ms_disp * 1e6),
         },
     }
 

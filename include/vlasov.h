@@ -281,6 +281,26 @@ int vlasov_moments(const vlasov_grid* grid, vlasov_prec prec, const void* f, con
                    double* rho, double* umean, double* mass, void* stream);
 
 /*
+ * The velocity moments up to second order per spatial cell, the velocity
+ * dispersion tensor among them (section 5.1.3 names it with the density and
+ * mean velocity as moments needing no data exchange; the paper gives no
+ * formula, and it is read as the density-weighted covariance of u):
+ *   rho[c], umean[a][c]  as vlasov_moments (umean may be NULL)
+ *   sigma[k][c] = sum_u (u_l - umean_l)(u_m - umean_m) f / sum_u f, with
+ *                 (l,m) = xx, xy, xz, yy, yz, zz for k = 0..5; 0 where
+ *                 rho[c] = 0.
+ * One pass over f: FP64 sums of f, u f and u_l u_m f about u = 0, then sigma =
+ * <u_l u_m> - umean_l umean_m, which keeps about 16 - log10(<u^2>/sigma)
+ * digits.  rho [nx][ny][nz], umean [3][...], sigma [6][...]: FP64 device.
+ * Errors: VLASOV_ERR_NULL (grid, f, rho or sigma NULL), VLASOV_ERR_SHAPE,
+ * VLASOV_ERR_PREC (unknown precision; FP16/BF16 without scale),
+ * VLASOV_ERR_ALIAS (rho, umean, sigma overlap), VLASOV_ERR_DEVICE.
+ */
+int vlasov_dispersion(const vlasov_grid* grid, vlasov_prec prec, const void* f,
+                      const float* scale, double* rho, double* umean, double* sigma,
+                      void* stream);
+
+/*
  * Derivatives (FP32 storage only).  With the limiter's selections frozen at
  * the forward input f_in -- the forward arithmetic is re-run on f_in and each
  * minimum, maximum, median, minmod and clamp keeps the argument it selected

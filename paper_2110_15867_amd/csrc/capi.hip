@@ -217,7 +217,7 @@ size_t lds_limit()
 // Moments of f (arguments checked by the caller): rho, umean per cell, and the
 // total mass when `mass` is given.
 int run_moments(const vlasov_grid* g, const Dims& d, int prec, const void* f, const float* scale,
-                double* rho, double* umean, double* mass, hipStream_t st)
+                double* rho, double* umean, double* mass, hipStream_t st, double* sigma = nullptr)
 {
     MomArgs a;
     memset(&a, 0, sizeof(a));
@@ -233,6 +233,7 @@ int run_moments(const vlasov_grid* g, const Dims& d, int prec, const void* f, co
     }
     a.rho = rho;
     a.umean = umean;
+    a.sigma = sigma;
     int rc = from_hip(launch_moments(prec, f, scale, a, st));
     if (rc || mass == nullptr) return rc;
     const double dx3 = (g->L[0] / g->n[0]) * (g->L[1] / g->n[1]) * (g->L[2] / g->n[2]);
@@ -597,6 +598,26 @@ int vlasov_moments(const vlasov_grid* g, vlasov_prec prec, const void* f, const 
     if (mass != nullptr && (overlap(mass, 8, rho, nb) || overlap(mass, 8, umean, 3 * nb)))
         return VLASOV_ERR_ALIAS;
     return run_moments(g, d, prec, f, scale, rho, umean, mass, (hipStream_t)stream);
+}
+
+int vlasov_dispersion(const vlasov_grid* g, vlasov_prec prec, const void* f, const float* scale,
+                      double* rho, double* umean, double* sigma, void* stream)
+{
+    Dims d;
+    if (g == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (!prec_ok(prec)) return VLASOV_ERR_PREC;
+    if (f == nullptr || rho == nullptr || sigma == nullptr) return VLASOV_ERR_NULL;
+    if (!aligned16(f)) return VLASOV_ERR_SHAPE;
+    if (prec != VLASOV_F32) {
+        if (scale == nullptr) return VLASOV_ERR_PREC;
+        if (!scaled_shape_ok(d)) return VLASOV_ERR_SHAPE;
+    }
+    const size_t nb = (size_t)d.cells * sizeof(double);
+    if (overlap(rho, nb, sigma, 6 * nb) || overlap(umean, 3 * nb, rho, nb) ||
+        overlap(umean, 3 * nb, sigma, 6 * nb))
+        return VLASOV_ERR_ALIAS;
+    return run_moments(g, d, prec, f, scale, rho, umean, nullptr, (hipStream_t)stream, sigma);
 }
 
 size_t vlasov_step_sc_workspace_bytes(const vlasov_grid* grid, vlasov_prec prec)

@@ -88,6 +88,7 @@ struct MomArgs {
     double* rho;
     double* umean;   // [3][cells] or nullptr
     long nuz;
+    double* sigma;   // [6][cells] dispersion tensor (xx, xy, xz, yy, yz, zz) or nullptr
 };
 hipError_t launch_moments(int prec, const void* f, const float* scale, const MomArgs& a,
                           hipStream_t st);

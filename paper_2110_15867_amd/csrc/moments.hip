@@ -17,15 +17,23 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int P, int V>
+// With SIG, also the second moments about u = 0, from which the dispersion
+// tensor of each cell follows as sum u_l u_m f / sum f - umean_l umean_m.  The
+// sums are FP64 over FP32 (or decoded FP16/BF16) values, so the subtraction
+// loses about log10(<u^2> / sigma) digits of the 16 FP64 carries.
+template <int P, int V, bool SIG>
 __global__ void __launch_bounds__(256) k_moments(const typename Codec<P>::T* __restrict__ f,
                                                  const float* __restrict__ scale, MomArgs a)
 {
-    __shared__ double red[4][4];
+    constexpr int NS = SIG ? 10 : 4;
+    __shared__ double red[4][NS];
     const long cell = blockIdx.x;
     const typename Codec<P>::T* blk = f + cell * a.Nu;
     const long nyz = (long)a.nu[1] * a.nu[2];
-    double m0 = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+    // m[0] = sum f, m[1..3] = sum u f, m[4..9] = sum u_l u_m f (xx xy xz yy yz zz)
+    double m[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) m[k] = 0.0;
     for (long e = (long)threadIdx.x * V; e < a.Nu; e += (long)blockDim.x * V) {
         const long jx = e / nyz;
         const long jy = (e - jx * nyz) / a.nu[2];
@@ -36,40 +44,69 @@ __global__ void __launch_bounds__(256) k_moments(const typename Codec<P>::T* __r
         load_row<P, V>(blk + e, sc, x);
         const double ux = a.umin[0] + ((double)jx + 0.5) * a.du[0];
         const double uy = a.umin[1] + ((double)jy + 0.5) * a.du[1];
-        double s0 = 0.0, sz = 0.0;
+        double s0 = 0.0, sz = 0.0, szz = 0.0;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const double xv = (double)x[v];
             const double uz = a.umin[2] + ((double)(jz + v) + 0.5) * a.du[2];
             s0 += xv;
             sz = fma(uz, xv, sz);
+            if (SIG) szz = fma(uz * uz, xv, szz);
         }
-        m0 += s0;
-        mx = fma(ux, s0, mx);
-        my = fma(uy, s0, my);
-        mz += sz;
+        m[0] += s0;
+        m[1] = fma(ux, s0, m[1]);
+        m[2] = fma(uy, s0, m[2]);
+        m[3] += sz;
+        if (SIG) {
+            m[4] = fma(ux * ux, s0, m[4]);
+            m[5] = fma(ux * uy, s0, m[5]);
+            m[6] = fma(ux, sz, m[6]);
+            m[7] = fma(uy * uy, s0, m[7]);
+            m[8] = fma(uy, sz, m[8]);
+            m[9] += szz;
+        }
     }
-    m0 = wave_sum(m0);
-    mx = wave_sum(mx);
-    my = wave_sum(my);
-    mz = wave_sum(mz);
+#pragma unroll
+    for (int k = 0; k < NS; ++k) m[k] = wave_sum(m[k]);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
-        red[wave][0] = m0; red[wave][1] = mx; red[wave][2] = my; red[wave][3] = mz;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) red[wave][k] = m[k];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double t[4] = {0.0, 0.0, 0.0, 0.0};
+        double t[NS];
+        for (int c = 0; c < NS; ++c) t[c] = 0.0;
         const int nw = (blockDim.x + 63) >> 6;
         for (int q = 0; q < nw; ++q)
-            for (int c = 0; c < 4; ++c) t[c] += red[q][c];
+            for (int c = 0; c < NS; ++c) t[c] += red[q][c];
         a.rho[cell] = t[0] * a.du3;
+        const double inv = t[0] != 0.0 ? 1.0 / t[0] : 0.0;
+        const double um[3] = {t[1] * inv, t[2] * inv, t[3] * inv};
         if (a.umean != nullptr) {
-            const double inv = t[0] != 0.0 ? 1.0 / t[0] : 0.0;
-            a.umean[cell] = t[1] * inv;
-            a.umean[a.cells + cell] = t[2] * inv;
-            a.umean[2 * a.cells + cell] = t[3] * inv;
+            a.umean[cell] = um[0];
+            a.umean[a.cells + cell] = um[1];
+            a.umean[2 * a.cells + cell] = um[2];
         }
+        if (SIG) {
+            const int l[6] = {0, 0, 0, 1, 1, 2}, r[6] = {0, 1, 2, 1, 2, 2};
+            for (int k = 0; k < 6; ++k)
+                a.sigma[(long)k * a.cells + cell] =
+                    t[0] != 0.0 ? fma(t[4 + k], inv, -um[l[k]] * um[r[k]]) : 0.0;
+        }
+    }
+}
+
+template <int P, bool SIG>
+static void launch_moments_sig(const typename Codec<P>::T* f, const float* scale,
+                               const MomArgs& a, hipStream_t st)
+{
+    if (a.nuz % 4 == 0) {
+        hipLaunchKernelGGL((k_moments<P, 4, SIG>), dim3((unsigned)a.cells), dim3(256), 0, st, f,
+                           scale, a);
+    } else {
+        hipLaunchKernelGGL((k_moments<P, 1, SIG>), dim3((unsigned)a.cells), dim3(256), 0, st, f,
+                           scale, a);
     }
 }
 
@@ -79,13 +116,10 @@ static hipError_t launch_moments_p(const void* f, const float* scale, const MomA
 {
     using T = typename Codec<P>::T;
     if (a.cells == 0) return hipSuccess;
-    if (a.nuz % 4 == 0) {
-        hipLaunchKernelGGL((k_moments<P, 4>), dim3((unsigned)a.cells), dim3(256), 0, st,
-                           (const T*)f, scale, a);
-    } else {
-        hipLaunchKernelGGL((k_moments<P, 1>), dim3((unsigned)a.cells), dim3(256), 0, st,
-                           (const T*)f, scale, a);
-    }
+    if (a.sigma != nullptr)
+        launch_moments_sig<P, true>((const T*)f, scale, a, st);
+    else
+        launch_moments_sig<P, false>((const T*)f, scale, a, st);
     return hipGetLastError();
 }
 

@@ -93,6 +93,8 @@ def _load():
     L.vlasov_step_moments.argtypes = [G, I, I, P, P, P, P, P, P, D, D, P, S, P, P, P, P]
     L.vlasov_moments.restype = I
     L.vlasov_moments.argtypes = [G, I, P, P, P, P, P, P]
+    L.vlasov_dispersion.restype = I
+    L.vlasov_dispersion.argtypes = [G, I, P, P, P, P, P, P]
     L.vlasov_sum_f64.restype = I
     L.vlasov_sum_f64.argtypes = [P, ctypes.c_int64, P, P]
     L.vlasov_stream_copy.restype = I
@@ -283,6 +285,11 @@ def vlasov_moments(grid, prec, f, scale, rho, umean, mass, stream=None):
                                _ptr(umean), _ptr(mass), _stream(stream)), "vlasov_moments")
 
 
+def vlasov_dispersion(grid, prec, f, scale, rho, umean, sigma, stream=None):
+    _check(_lib.vlasov_dispersion(ctypes.byref(grid), prec, _ptr(f), _ptr(scale), _ptr(rho),
+                                  _ptr(umean), _ptr(sigma), _stream(stream)), "vlasov_dispersion")
+
+
 def vlasov_sum_f64(x, n, out, stream=None):
     _check(_lib.vlasov_sum_f64(_ptr(x), int(n), _ptr(out), _stream(stream)), "vlasov_sum_f64")
 
@@ -431,3 +438,14 @@ def moments(state: State, with_mean=True, stream=None):
     mass = torch.empty((), dtype=torch.float64, device=dev)
     vlasov_moments(state.grid, state.prec, state.f, state.scale, rho, um, mass, stream)
     return rho, um, mass
+
+
+def dispersion(state: State, stream=None):
+    """(rho, umean, sigma): sigma [6][nx][ny][nz] in the order xx, xy, xz, yy, yz, zz."""
+    n = tuple(state.grid.n)
+    dev = state.f.device
+    rho = torch.empty(n, dtype=torch.float64, device=dev)
+    um = torch.empty((3,) + n, dtype=torch.float64, device=dev)
+    sig = torch.empty((6,) + n, dtype=torch.float64, device=dev)
+    vlasov_dispersion(state.grid, state.prec, state.f, state.scale, rho, um, sig, stream)
+    return rho, um, sig

@@ -62,6 +62,10 @@ def test_host_side_entry_points(lib):
                          None, 0, None, None) == -1
     bad = V.make_grid((4, 0, 4), (8, 8, 8))
     assert L.vlasov_moments(ctypes.byref(bad), 0, None, None, None, None, None, None) == -2
+    assert L.vlasov_dispersion(None, 0, None, None, None, None, None, None) == -1
+    assert L.vlasov_dispersion(ctypes.byref(bad), 0, None, None, None, None, None, None) == -2
+    assert L.vlasov_dispersion(ctypes.byref(g), 0, ctypes.c_void_p(256), None,
+                               ctypes.c_void_p(512), None, None, None) == -1
 
 
 def test_product_path_does_not_touch_the_oracle():
