@@ -271,6 +271,43 @@ int vlasov_step_sc(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, co
                    void* work, size_t work_bytes, double* outflow, void* stream);
 
 /*
+ * Background expansion for comoving runs: Eq. (1) drifts comoving positions
+ * at u / a(t)^2 and Eq. (2) carries 4 pi G a(t)^2 (rho - mean rho).  The
+ * background is a flat universe of matter (omega_m) and a cosmological
+ * constant (1 - omega_m), radiation neglected, H0 in the inverse time unit of
+ * dt; a(t) is the closed-form solution of its Friedmann equation, t cosmic
+ * time from the big bang.  Host functions, no device work.
+ *
+ *   vlasov_cosmo_a:     *a = a(t)
+ *   vlasov_cosmo_t:     *t = t(a) (e.g. the start time of a run at redshift
+ *                       z: a = 1 / (1 + z))
+ *   vlasov_cosmo_steps: for steps of dt from t0, host arrays
+ *                       a[k] = a(t0 + k dt), k = 0..nsteps (a may be NULL),
+ *                       a2inv[n] = (1/dt) * integral of dt'/a(t')^2 over
+ *                       step n (adaptive Gauss-Legendre, relative 1e-15):
+ *                       the a2inv argument of vlasov_step, vlasov_step_sc
+ *                       or vlasov_steps for that step, which moves a
+ *                       position by u times the integral (u is constant
+ *                       during the drift).
+ * For a comoving f the density rho = sum f du^3 keeps its mean, and Eq. (2)
+ * reads nabla^2 phi = (K / a)(rho - mean rho), K = 4 pi G times the physical
+ * density of one unit of rho at a = 1: the coupling of vlasov_step_sc for
+ * step n is K / a[n+1] (its field is taken at t0 + (n+1) dt).
+ * Errors: VLASOV_ERR_NULL (cosmology or an output NULL), VLASOV_ERR_NONFINITE
+ * (t, a, t0 or dt not finite), VLASOV_ERR_SHAPE (omega_m outside (0, 1],
+ * H0 <= 0, t, a, t0 or dt <= 0, nsteps < 1).
+ */
+typedef struct vlasov_cosmology {
+    double omega_m;   /* matter density parameter today, 0 < omega_m <= 1 */
+    double H0;        /* Hubble constant today, in 1 / (time unit of dt) */
+} vlasov_cosmology;
+
+int vlasov_cosmo_a(const vlasov_cosmology* cosmo, double t, double* a);
+int vlasov_cosmo_t(const vlasov_cosmology* cosmo, double a, double* t);
+int vlasov_cosmo_steps(const vlasov_cosmology* cosmo, double t0, double dt, int nsteps,
+                       double* a, double* a2inv);
+
+/*
  * Velocity moments per spatial cell (section 5.1.3), accumulated in FP64:
  *   rho[c]      = sum_u f du^3
  *   umean[a][c] = sum_u u_a f du^3 / rho[c]  (0 where rho[c] = 0); may be NULL

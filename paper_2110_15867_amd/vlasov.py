@@ -37,6 +37,10 @@ class vlasov_grid(ctypes.Structure):
                 ("L", ctypes.c_double * 3), ("umax", ctypes.c_double * 3)]
 
 
+class vlasov_cosmology(ctypes.Structure):
+    _fields_ = [("omega_m", ctypes.c_double), ("H0", ctypes.c_double)]
+
+
 def make_grid(n, nu, L=(1.0, 1.0, 1.0), umax=(1.0, 1.0, 1.0)) -> vlasov_grid:
     g = vlasov_grid()
     for a in range(3):
@@ -93,6 +97,14 @@ def _load():
     L.vlasov_step_moments.argtypes = [G, I, I, P, P, P, P, P, P, D, D, P, S, P, P, P, P]
     L.vlasov_moments.restype = I
     L.vlasov_moments.argtypes = [G, I, P, P, P, P, P, P]
+    C = ctypes.POINTER(vlasov_cosmology)
+    DP = ctypes.POINTER(ctypes.c_double)
+    L.vlasov_cosmo_a.restype = I
+    L.vlasov_cosmo_a.argtypes = [C, D, DP]
+    L.vlasov_cosmo_t.restype = I
+    L.vlasov_cosmo_t.argtypes = [C, D, DP]
+    L.vlasov_cosmo_steps.restype = I
+    L.vlasov_cosmo_steps.argtypes = [C, D, D, I, DP, DP]
     L.vlasov_dispersion.restype = I
     L.vlasov_dispersion.argtypes = [G, I, P, P, P, P, P, P]
     L.vlasov_sum_f64.restype = I
@@ -283,6 +295,27 @@ def vlasov_step_moments(grid, prec, vbc, f_in, scale_in, f_out, scale_out, g_n, 
 def vlasov_moments(grid, prec, f, scale, rho, umean, mass, stream=None):
     _check(_lib.vlasov_moments(ctypes.byref(grid), prec, _ptr(f), _ptr(scale), _ptr(rho),
                                _ptr(umean), _ptr(mass), _stream(stream)), "vlasov_moments")
+
+
+def vlasov_cosmo_a(cosmo, t) -> float:
+    a = ctypes.c_double()
+    _check(_lib.vlasov_cosmo_a(ctypes.byref(cosmo), float(t), ctypes.byref(a)), "vlasov_cosmo_a")
+    return a.value
+
+
+def vlasov_cosmo_t(cosmo, a) -> float:
+    t = ctypes.c_double()
+    _check(_lib.vlasov_cosmo_t(ctypes.byref(cosmo), float(a), ctypes.byref(t)), "vlasov_cosmo_t")
+    return t.value
+
+
+def vlasov_cosmo_steps(cosmo, t0, dt, nsteps):
+    """(a [nsteps + 1], a2inv [nsteps]) as lists of floats."""
+    a = (ctypes.c_double * (nsteps + 1))()
+    a2 = (ctypes.c_double * max(nsteps, 1))()
+    _check(_lib.vlasov_cosmo_steps(ctypes.byref(cosmo), float(t0), float(dt), int(nsteps), a, a2),
+           "vlasov_cosmo_steps")
+    return list(a), list(a2)[:nsteps]
 
 
 def vlasov_dispersion(grid, prec, f, scale, rho, umean, sigma, stream=None):

@@ -1,0 +1,59 @@
+"""The library's background expansion (host functions, no GPU): a(t), t(a) and
+the per-step drift factors against the oracle's Friedmann quadrature, and the
+argument errors."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cosmology as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if not os.path.exists(os.path.join(ROOT, "paper_2110_15867_amd", "libvlasov.so")):
+    pytest.skip("libvlasov.so not built", allow_module_level=True)
+
+from paper_2110_15867_amd import vlasov as V  # noqa: E402
+
+
+def _cosmo(om, H0):
+    c = V.vlasov_cosmology()
+    c.omega_m, c.H0 = om, H0
+    return c
+
+
+@pytest.mark.parametrize("om,H0", [(1.0, 1.0), (0.3, 1.0), (0.31, 0.07), (0.05, 2.0)])
+def test_scale_factor_and_time(om, H0):
+    c = _cosmo(om, H0)
+    for z in (100.0, 10.0, 1.0, 0.0):
+        a = 1.0 / (1.0 + z)
+        t = V.vlasov_cosmo_t(c, a)
+        assert t == pytest.approx(C.time_of_a(om, H0, a), rel=1e-12)
+        assert V.vlasov_cosmo_a(c, t) == pytest.approx(a, rel=1e-13)
+
+
+@pytest.mark.parametrize("om,H0", [(1.0, 1.0), (0.3, 1.0), (0.31, 0.07)])
+def test_step_factors_against_oracle(om, H0):
+    c = _cosmo(om, H0)
+    t0 = V.vlasov_cosmo_t(c, 1.0 / 11.0)                 # start at redshift 10
+    dt = 0.4 * t0                                         # long steps: a grows by ~25% each
+    a, a2inv = V.vlasov_cosmo_steps(c, t0, dt, 4)
+    a_o, a2_o = C.steps(om, H0, t0, dt, 4)
+    np.testing.assert_allclose(a, a_o, rtol=1e-12)
+    np.testing.assert_allclose(a2inv, a2_o, rtol=1e-12)
+
+
+def test_errors():
+    L = V.lib()
+    c = _cosmo(0.3, 1.0)
+    out = (V.ctypes.c_double * 4)()
+    assert L.vlasov_cosmo_steps(None, 1.0, 0.1, 2, out, out) == -1
+    assert L.vlasov_cosmo_steps(V.ctypes.byref(c), 1.0, 0.1, 2, None, None) == -1
+    assert L.vlasov_cosmo_steps(V.ctypes.byref(c), 1.0, 0.1, 0, out, out) == -2
+    assert L.vlasov_cosmo_steps(V.ctypes.byref(c), 1.0, -0.1, 2, out, out) == -2
+    assert L.vlasov_cosmo_steps(V.ctypes.byref(c), float("nan"), 0.1, 2, out, out) == -5
+    for bad in (_cosmo(0.0, 1.0), _cosmo(1.2, 1.0), _cosmo(0.3, 0.0)):
+        with pytest.raises(V.VlasovError) as e:
+            V.vlasov_cosmo_a(bad, 1.0)
+        assert e.value.code == -2
+    with pytest.raises(V.VlasovError):
+        V.vlasov_cosmo_t(c, 0.0)
