@@ -21,7 +21,9 @@ __device__ __forceinline__ double wave_sum(double v)
 // tensor of each cell follows as sum u_l u_m f / sum f - umean_l umean_m.  The
 // sums are FP64 over FP32 (or decoded FP16/BF16) values, so the subtraction
 // loses about log10(<u^2> / sigma) digits of the 16 FP64 carries.
-template <int P, int V, bool SIG>
+// ZC: nu_z divides the trip stride 256 V, so every row a thread reads starts
+// at the same jz and its V values of u_z are computed once.
+template <int P, int V, bool SIG, bool ZC>
 __global__ void __launch_bounds__(256) k_moments(const typename Codec<P>::T* __restrict__ f,
                                                  const float* __restrict__ scale, MomArgs a)
 {
@@ -29,41 +31,70 @@ __global__ void __launch_bounds__(256) k_moments(const typename Codec<P>::T* __r
     __shared__ double red[4][NS];
     const long cell = blockIdx.x;
     const typename Codec<P>::T* blk = f + cell * a.Nu;
-    const long nyz = (long)a.nu[1] * a.nu[2];
     // m[0] = sum f, m[1..3] = sum u f, m[4..9] = sum u_l u_m f (xx xy xz yy yz zz)
     double m[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) m[k] = 0.0;
-    for (long e = (long)threadIdx.x * V; e < a.Nu; e += (long)blockDim.x * V) {
-        const long jx = e / nyz;
-        const long jy = (e - jx * nyz) / a.nu[2];
-        const long jz = e - jx * nyz - jy * a.nu[2];
-        float sc = 1.0f;
-        if (Codec<P>::scaled) sc = scale[cell * (a.Nu / a.nuz) + e / a.nuz];
-        float x[V];
-        load_row<P, V>(blk + e, sc, x);
-        const double ux = a.umin[0] + ((double)jx + 0.5) * a.du[0];
-        const double uy = a.umin[1] + ((double)jy + 0.5) * a.du[1];
-        double s0 = 0.0, sz = 0.0, szz = 0.0;
+    // U rows per thread and trip: their loads are issued before any of them
+    // is summed, so each wave keeps U loads in flight.  Rows past the block
+    // read nothing and add zeros.  Offsets inside a block fit 32 bits (the
+    // library refuses larger velocity blocks), so the index arithmetic is
+    // 32-bit; the trip counter is 64-bit so that it cannot wrap.
+    constexpr int U = 4;
+    const long nb = a.Nu, stride = (long)blockDim.x * V;
+    const int nz = a.nu[2], ny = a.nu[1];
+    double uzc[V];
+    if (ZC) {
+        const int jz0 = (int)((threadIdx.x * V) % nz);
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const double xv = (double)x[v];
-            const double uz = a.umin[2] + ((double)(jz + v) + 0.5) * a.du[2];
-            s0 += xv;
-            sz = fma(uz, xv, sz);
-            if (SIG) szz = fma(uz * uz, xv, szz);
+        for (int v = 0; v < V; ++v) uzc[v] = a.umin[2] + ((double)(jz0 + v) + 0.5) * a.du[2];
+    }
+    for (long e0 = (long)threadIdx.x * V; e0 < nb; e0 += U * stride) {
+        float x[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long e = e0 + u * stride;
+            if (e < nb) {
+                float sc = 1.0f;
+                if (Codec<P>::scaled) sc = scale[cell * (a.Nu / a.nuz) + (int)e / nz];
+                load_row<P, V>(blk + e, sc, x[u]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) x[u][v] = 0.0f;
+            }
         }
-        m[0] += s0;
-        m[1] = fma(ux, s0, m[1]);
-        m[2] = fma(uy, s0, m[2]);
-        m[3] += sz;
-        if (SIG) {
-            m[4] = fma(ux * ux, s0, m[4]);
-            m[5] = fma(ux * uy, s0, m[5]);
-            m[6] = fma(ux, sz, m[6]);
-            m[7] = fma(uy * uy, s0, m[7]);
-            m[8] = fma(uy, sz, m[8]);
-            m[9] += szz;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long el = e0 + u * stride;
+            const int e = el < nb ? (int)el : 0;         // rows past the block hold zeros
+            const int row = e / nz;                      // jx * ny + jy
+            const int jz = e - row * nz;
+            const int jx = row / ny;
+            const int jy = row - jx * ny;
+            const double ux = a.umin[0] + ((double)jx + 0.5) * a.du[0];
+            const double uy = a.umin[1] + ((double)jy + 0.5) * a.du[1];
+            double s0 = 0.0, sz = 0.0, szz = 0.0;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const double xv = (double)x[u][v];
+                const double uz =
+                    ZC ? uzc[v] : a.umin[2] + ((double)(jz + v) + 0.5) * a.du[2];
+                s0 += xv;
+                sz = fma(uz, xv, sz);
+                if (SIG) szz = fma(uz * uz, xv, szz);
+            }
+            m[0] += s0;
+            m[1] = fma(ux, s0, m[1]);
+            m[2] = fma(uy, s0, m[2]);
+            m[3] += sz;
+            if (SIG) {
+                m[4] = fma(ux * ux, s0, m[4]);
+                m[5] = fma(ux * uy, s0, m[5]);
+                m[6] = fma(ux, sz, m[6]);
+                m[7] = fma(uy * uy, s0, m[7]);
+                m[8] = fma(uy, sz, m[8]);
+                m[9] += szz;
+            }
         }
     }
 #pragma unroll
@@ -97,17 +128,30 @@ __global__ void __launch_bounds__(256) k_moments(const typename Codec<P>::T* __r
     }
 }
 
+template <int P, int V, bool SIG>
+static void launch_moments_v(const typename Codec<P>::T* f, const float* scale, const MomArgs& a,
+                             hipStream_t st)
+{
+    if ((256 * V) % a.nuz == 0)
+        hipLaunchKernelGGL((k_moments<P, V, SIG, true>), dim3((unsigned)a.cells), dim3(256), 0,
+                           st, f, scale, a);
+    else
+        hipLaunchKernelGGL((k_moments<P, V, SIG, false>), dim3((unsigned)a.cells), dim3(256), 0,
+                           st, f, scale, a);
+}
+
 template <int P, bool SIG>
 static void launch_moments_sig(const typename Codec<P>::T* f, const float* scale,
                                const MomArgs& a, hipStream_t st)
 {
-    if (a.nuz % 4 == 0) {
-        hipLaunchKernelGGL((k_moments<P, 4, SIG>), dim3((unsigned)a.cells), dim3(256), 0, st, f,
-                           scale, a);
-    } else {
-        hipLaunchKernelGGL((k_moments<P, 1, SIG>), dim3((unsigned)a.cells), dim3(256), 0, st, f,
-                           scale, a);
-    }
+    // 16-byte loads: 4 FP32 or 8 FP16/BF16 values of one uz-line
+    constexpr int V16 = 16 / sizeof(typename Codec<P>::T);
+    if (a.nuz % V16 == 0)
+        launch_moments_v<P, V16, SIG>(f, scale, a, st);
+    else if (a.nuz % 4 == 0)
+        launch_moments_v<P, 4, SIG>(f, scale, a, st);
+    else
+        launch_moments_v<P, 1, SIG>(f, scale, a, st);
 }
 
 template <int P>
