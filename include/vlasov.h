@@ -284,7 +284,7 @@ int vlasov_step_sc(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, co
  *   vlasov_cosmo_steps: for steps of dt from t0, host arrays
  *                       a[k] = a(t0 + k dt), k = 0..nsteps (a may be NULL),
  *                       a2inv[n] = (1/dt) * integral of dt'/a(t')^2 over
- *                       step n (adaptive Gauss-Legendre, relative 1e-15):
+ *                       step n (adaptive Gauss-Legendre, relative 1e-14):
  *                       the a2inv argument of vlasov_step, vlasov_step_sc
  *                       or vlasov_steps for that step, which moves a
  *                       position by u times the integral (u is constant
@@ -294,8 +294,8 @@ int vlasov_step_sc(const vlasov_grid* grid, vlasov_prec prec, vlasov_vbc vbc, co
  * density of one unit of rho at a = 1: the coupling of vlasov_step_sc for
  * step n is K / a[n+1] (its field is taken at t0 + (n+1) dt).
  * Errors: VLASOV_ERR_NULL (cosmology or an output NULL), VLASOV_ERR_NONFINITE
- * (t, a, t0 or dt not finite), VLASOV_ERR_SHAPE (omega_m outside (0, 1],
- * H0 <= 0, t, a, t0 or dt <= 0, nsteps < 1).
+ * (t, a, t0 or dt not finite, or a result overflows), VLASOV_ERR_SHAPE
+ * (omega_m outside (0, 1], H0 <= 0, t, a, t0 or dt <= 0, nsteps < 1).
  */
 typedef struct vlasov_cosmology {
     double omega_m;   /* matter density parameter today, 0 < omega_m <= 1 */

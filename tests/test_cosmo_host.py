@@ -57,3 +57,17 @@ def test_errors():
         assert e.value.code == -2
     with pytest.raises(V.VlasovError):
         V.vlasov_cosmo_t(c, 0.0)
+    with pytest.raises(V.VlasovError) as e:                # a(t) overflows
+        V.vlasov_cosmo_a(c, 1e6)
+    assert e.value.code == -5
+
+
+def test_quadrature_terminates_near_the_big_bang():
+    """A first step that starts next to t = 0, where 1/a^2 ~ t^(-4/3) varies
+    over many decades: the drift integral still matches the Einstein-de
+    Sitter closed form and returns."""
+    c = _cosmo(1.0, 1.0)
+    t0, dt = 1e-9, 1.0
+    _, a2inv = V.vlasov_cosmo_steps(c, t0, dt, 1)
+    want = 3 * 1.5 ** (-4 / 3) * (t0 ** (-1 / 3) - (t0 + dt) ** (-1 / 3))
+    assert a2inv[0] * dt == pytest.approx(want, rel=1e-10)
