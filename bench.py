@@ -55,22 +55,33 @@ def algorithmic_bytes_per_cell(prec: int, nuz: int) -> float:
     return 2.0 * (2.0 + 4.0 / nuz)
 
 
-def measured_traffic(prec: int, kernel: str, nu: int, nx: int):
-    """HBM bytes per dispatch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (else None)."""
-    import glob
+# The sources of the profiled kernels (the kick, the position sweeps, the copy
+# kernel that calibrates the counters) and of the host code that launches
+# them; the moments, field, adjoint and background files hold none of them.
+TRAFFIC_SOURCES = ("capi.hip", "kick.hip", "launch.hpp", "probe.hip", "rows.hpp", "sl_mpp5.hpp",
+                   "sweeps.hip", "sweeps_bf16.hip", "sweeps_f16.hip", "sweeps_f32.hip",
+                   "sweeps_impl.hpp")
+
+
+def kernel_source_hash() -> str:
     import hashlib
 
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_2110_15867_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(prec: int, kernel: str, nu: int, nx: int):
+    """HBM bytes per dispatch from the committed rocprofv3 counter summary, if it
+    was taken on the current sources of the profiled kernels (else None)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
-    h = hashlib.sha256()
-    for fn in sorted(glob.glob(os.path.join(ROOT, "paper_2110_15867_amd", "csrc", "*"))):
-        h.update(os.path.basename(fn).encode())
-        with open(fn, "rb") as fh:
-            h.update(fh.read())
     data = json.load(open(path)).get({0: "f32", 1: "f16", 2: "bf16"}[prec])
-    if not data or data.get("source_sha256") != h.hexdigest():
+    if not data or data.get("source_sha256") != kernel_source_hash():
         return None
     if kernel == "kick":
         prefix = f"k_kick<{prec}, {nu}, "
