@@ -9,7 +9,11 @@ systems; for a growing mode exp(gamma t), with y = gamma / (sqrt(2) k sigma),
     (k sigma / omega_J)^2 = 1 - sqrt(pi) y erfcx(y),
 (the plasma-dispersion function at an imaginary argument).  It tends to
 gamma = omega_J for a cold system and to 0 at the Jeans wavenumber
-k = omega_J / sigma.  The input holds none of the method's arithmetic.
+k = omega_J / sigma.  Above it the mode is damped without oscillating,
+exp(-delta t), the same relation continued to a negative imaginary
+frequency: with y = delta / (sqrt(2) k sigma),
+    (k sigma / omega_J)^2 = 1 + sqrt(pi) y erfcx(-y).
+The input holds none of the method's arithmetic.
 """
 import numpy as np
 from scipy import optimize, special
@@ -27,6 +31,12 @@ DT = 0.05
 def growth_rate(k_sigma_over_wj: float, k: float = K, sigma: float = SIGMA) -> float:
     r2 = k_sigma_over_wj ** 2
     y = optimize.brentq(lambda y: 1 - np.sqrt(np.pi) * y * special.erfcx(y) - r2, 1e-9, 1e3)
+    return np.sqrt(2) * k * sigma * y
+
+
+def damping_rate(k_sigma_over_wj: float, k: float = K, sigma: float = SIGMA) -> float:
+    r2 = k_sigma_over_wj ** 2
+    y = optimize.brentq(lambda y: 1 + np.sqrt(np.pi) * y * special.erfcx(-y) - r2, 1e-9, 10.0)
     return np.sqrt(2) * k * sigma * y
 
 
