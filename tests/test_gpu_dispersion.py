@@ -78,21 +78,28 @@ def test_sampled_gaussian_on_the_device():
         assert np.abs(um.cpu().numpy()[:, 0, 0, k] - u0).max() < 1e-6
 
 
-def test_full_size_sampled_cells():
-    """The 64^3 x 32^3 workload's initial f (FP32): sampled cells against the
-    oracle on a one-cell grid, and the tensor symmetric positive
-    semi-definite in every cell."""
+@pytest.mark.parametrize("prec", [V.F32, V.F16])
+def test_full_size_sampled_cells(prec):
+    """The 64^3 x 32^3 workload's initial f (FP32, and encoded to FP16):
+    sampled cells against the oracle on a one-cell grid (on the decoded
+    values), and the tensor symmetric positive semi-definite in every cell."""
     w = inputs.workload(3)
-    print("case: dispersion full size", w.name, flush=True)
+    print("case: dispersion full size", V.PREC_NAME[prec], w.name, flush=True)
     hg = V.make_grid(w.n, w.nu, w.L, w.umax)
-    st = V.State(hg, V.F32, inputs.initial_f32_device(w))
+    if prec == V.F32:
+        st = V.State(hg, V.F32, inputs.initial_f32_device(w))
+    else:
+        st = V.encode(hg, prec, inputs.initial_f32_device(w))
     rho, um, sig = V.dispersion(st)
     torch.cuda.synchronize()
     og1 = oracle.Grid.make((1, 1, 1), w.nu, (1.0, 1.0, 1.0), w.umax)
     rng = np.random.default_rng(32)
     for _ in range(8):
         c = tuple(int(v) for v in rng.integers(0, w.n[0], 3))
-        blk = st.f[c].double().cpu().numpy()[None, None, None]
+        blk = st.f[c].float()
+        if prec != V.F32:                # the stored value: FP32 product code x scale
+            blk = blk * st.scale[c][..., None]
+        blk = blk.double().cpu().numpy()[None, None, None]
         want = oracle.dispersion(og1, blk)[:, 0, 0, 0]
         got = sig[(slice(None),) + c].cpu().numpy()
         assert np.all(np.abs(got - want) <= _bar(w.umax).reshape(6)), c
