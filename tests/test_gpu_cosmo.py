@@ -4,7 +4,8 @@ The device chain takes its drift factors and couplings from
 vlasov_cosmo_steps and calls vlasov_step_sc; the oracle chain
 (oracle.cosmology.run_sc) takes its own from the Friedmann quadrature.
 FP32 at the sweeps' bar, density and field as in the single self-consistent
-step."""
+step.  And linear theory: a cold growing mode in Einstein-de Sitter grows as
+the scale factor."""
 import numpy as np
 import pytest
 
@@ -60,3 +61,38 @@ def test_comoving_selfconsistent_run_against_oracle():
     assert np.abs(got - f_ref).max() <= nsteps * 1e-5 * f_ref.max()
     np.testing.assert_allclose(rho.cpu().numpy(), rho_ref, rtol=1e-6, atol=0)
     assert np.abs(g.cpu().numpy() - g_ref).max() <= 1e-5 * np.abs(g_ref).max()
+
+
+def test_growing_mode_follows_the_scale_factor_on_the_device():
+    """A cold density wave's growing mode in Einstein-de Sitter grows as
+    a / a0 (tests/growth_setup.py): the device chain to 1 %, and its final
+    mode amplitude against the oracle chain's."""
+    import growth_setup as G
+
+    print("case: comoving growing mode", G.N, G.NU, flush=True)
+    hg = V.make_grid(G.N, G.NU, G.L, G.UMAX)
+    og = oracle.Grid.make(G.N, G.NU, G.L, G.UMAX)
+    cos = V.vlasov_cosmology()
+    cos.omega_m, cos.H0 = G.OMEGA_M, G.H0
+    t0 = V.vlasov_cosmo_t(cos, G.A0)
+    dt = (V.vlasov_cosmo_t(cos, G.A1) - t0) / G.NSTEPS
+    a, a2inv = V.vlasov_cosmo_steps(cos, t0, dt, G.NSTEPS)
+    f0 = G.initial_f().astype(np.float32)
+    st = V.State(hg, V.F32, torch.from_numpy(f0).cuda())
+    rho, _, _ = V.moments(st)
+    amp0 = G.mode_amplitude(rho.cpu().numpy())
+    g = V.field(hg, rho, G.COUPLING_K / a[0])
+    nb = V.vlasov_step_sc_workspace_bytes(hg, V.F32)
+    work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    for n in range(G.NSTEPS):
+        out = V.empty_state(hg, V.F32, "cuda")
+        g_new, rho_new = torch.empty_like(g), torch.empty_like(rho)
+        V.vlasov_step_sc(hg, V.F32, V.VBC_OUTFLOW, st.f, None, out.f, None, g, g_new, rho_new,
+                         G.COUPLING_K / a[n + 1], dt, a2inv[n], work, nb, None)
+        st, g, rho = out, g_new, rho_new
+    torch.cuda.synchronize()
+    amp1 = G.mode_amplitude(rho.cpu().numpy())
+    assert amp1 / amp0 == pytest.approx(G.A1 / G.A0, rel=1e-2)
+    _, _, rho_o, _, _ = C.run_sc(og, f0.astype(np.float64), G.COUPLING_K, G.OMEGA_M, G.H0, t0,
+                                 dt, G.NSTEPS)
+    assert amp1 == pytest.approx(G.mode_amplitude(rho_o), rel=1e-3)

@@ -5,7 +5,9 @@
 * the textbook ages H0 t(a=1) = 2/3 (Om = 1) and 0.9641 (Om = 0.3);
 * a(t) satisfies the Friedmann equation (central differences);
 * the drift integral is additive over split intervals and tends to
-  dt / a^2 for a short step.
+  dt / a^2 for a short step;
+* the comoving self-consistent loop (run_sc) grows a cold density wave's
+  growing mode as a / a0 in Einstein-de Sitter (see tests/growth_setup.py).
 """
 import numpy as np
 import pytest
@@ -50,3 +52,19 @@ def test_drift_integral_additive_and_short_step():
     a, a2inv = C.steps(om, H0, 0.2, 0.05, 3)
     assert a.shape == (4,) and a2inv.shape == (3,)
     assert np.all(np.diff(a) > 0) and np.all(a2inv < a[:-1] ** -2) and np.all(a2inv > a[1:] ** -2)
+
+
+def test_growing_mode_follows_the_scale_factor():
+    import oracle
+    import growth_setup as G
+
+    g = oracle.Grid.make(G.N, G.NU, G.L, G.UMAX)
+    f = G.initial_f()
+    rho, _, _ = oracle.moments(g, f)
+    assert rho.mean() == pytest.approx(1.0, rel=1e-12)
+    t0 = C.time_of_a(G.OMEGA_M, G.H0, G.A0)
+    dt = (C.time_of_a(G.OMEGA_M, G.H0, G.A1) - t0) / G.NSTEPS
+    _, _, rho1, a, _ = C.run_sc(g, f, G.COUPLING_K, G.OMEGA_M, G.H0, t0, dt, G.NSTEPS)
+    assert a[-1] == pytest.approx(G.A1, rel=1e-12)
+    growth = G.mode_amplitude(rho1) / G.mode_amplitude(rho)
+    assert growth == pytest.approx(G.A1 / G.A0, rel=1e-2)
