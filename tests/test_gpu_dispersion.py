@@ -25,6 +25,7 @@ SHAPES = {
     "v4": ((3, 4, 2), (16, 12, 16), (1.0, 1.0, 1.0), (1.0, 0.7, 1.3)),
     "ragged": ((2, 3, 5), (9, 7, 13), (1.0, 2.0, 1.0), (2.0, 1.0, 0.5)),
     "wide": ((2, 2, 2), (32, 32, 32), (1.0, 1.0, 1.0), (1.0, 1.0, 1.0)),
+    "nuz4": ((3, 2, 2), (6, 5, 4), (1.0, 1.0, 1.0), (0.8, 1.0, 1.2)),
 }
 COMP = oracle.DISPERSION_COMPONENTS
 
