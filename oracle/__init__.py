@@ -66,7 +66,9 @@ def lib():
         L.vor_sl5_weights.restype = None
         L.vor_sl5_weights.argtypes = [ctypes.c_double, c_double_p]
         L.vor_mp5_limit.restype = ctypes.c_double
-        L.vor_mp5_limit.argtypes = [ctypes.c_double] * 6
+        L.vor_mp5_limit.argtypes = [ctypes.c_double] * 7
+        L.vor_mp_alpha.restype = ctypes.c_double
+        L.vor_mp_alpha.argtypes = [ctypes.c_double]
         L.vor_split_shift.restype = None
         L.vor_split_shift.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_long), c_double_p]
         L.vor_interface_flux.restype = ctypes.c_double
@@ -153,8 +155,12 @@ def sl5_weights(mu: float) -> np.ndarray:
     return w
 
 
-def mp5_limit(fhat, a, b, c, d, e) -> float:
-    return lib().vor_mp5_limit(fhat, a, b, c, d, e)
+def mp5_limit(fhat, a, b, c, d, e, alpha) -> float:
+    return lib().vor_mp5_limit(fhat, a, b, c, d, e, alpha)
+
+
+def mp_alpha(mu: float) -> float:
+    return lib().vor_mp_alpha(mu)
 
 
 def split_shift(s: float):

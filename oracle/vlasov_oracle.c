@@ -22,9 +22,10 @@
  *     and by a positivity clamp, evaluated once per step (single stage);
  *   - velocity moments per spatial cell (section 5.1.3): density, mean
  *     velocity and the velocity dispersion tensor.
- * The paper prints no formula for the scheme; the readings taken here (alpha,
- * epsilon, the positivity form, the velocity boundary, the time level of the
- * field in the second half kick) are listed with the build's design notes.
+ * The paper prints no formula for the scheme; the readings taken here (the
+ * shift split and the shift-dependent alpha of the bounds, epsilon, the
+ * positivity form, the velocity boundary, the time level of the field in the
+ * second half kick) are listed with the build's design notes.
  *
  * Layout: f[ix][iy][iz][jx][jy][jz], jz fastest (the per-cell velocity block
  * of List 1 without its header).  Cell centres x_i = (i+1/2) dx and
@@ -32,9 +33,11 @@
  *
  * Parity status: the SL weights, the limiter, the line sweep, the composed
  * step and the moments are pinned by closed forms and invariants in the
- * CPU test-suite.  The limiter constant alpha = 4, the positivity clamp, the
- * vacuum velocity boundary and the field time level are readings of a silent
- * paper: parity against the paper itself is unpinned for those choices.
+ * CPU test-suite, among them the property the paper names for the scheme:
+ * repeated sweeps of monotone data create no new extrema at any shift.  The
+ * form of alpha, the positivity clamp, the vacuum velocity boundary and the
+ * field time level are readings of a silent paper: parity against the paper
+ * itself is unpinned for those choices.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -95,12 +98,12 @@ void vor_sl5_weights(double mu, double w[5])
 /* Monotonicity-preserving bounds of Suresh & Huynh (1997), the "standard   */
 /* MP preserving scheme" whose polynomial flux SL-MPP5 replaces (section     */
 /* 5.2).  Stencil a..e = f_{j-2..j+2} seen from the upwind side of the       */
-/* interface j+1/2.  alpha = 4 and epsilon = 0, so the limited value is the  */
-/* median of the unlimited value and the two bounds.                         */
+/* interface j+1/2.  epsilon = 0, so the limited value is the median of the  */
+/* unlimited value and the two bounds; alpha scales the upper limit          */
+/* f_UL = f_j + alpha (f_j - f_{j-1}).                                       */
 /* ------------------------------------------------------------------------ */
-double vor_mp5_limit(double fhat, double a, double b, double c, double d, double e)
+double vor_mp5_limit(double fhat, double a, double b, double c, double d, double e, double alpha)
 {
-    const double alpha = 4.0;
     double Dm = a - 2.0 * b + c;          /* curvature at j-1 */
     double D0 = b - 2.0 * c + d;          /* curvature at j   */
     double Dp = c - 2.0 * d + e;          /* curvature at j+1 */
@@ -113,6 +116,23 @@ double vor_mp5_limit(double fhat, double a, double b, double c, double d, double
     double fmin = dmax2(dmin3(c, d, fMD), dmin3(c, fUL, fLC));
     double fmax = dmin2(dmax3(c, d, fMD), dmax3(c, fUL, fLC));
     return vor_median3(fhat, fmin, fmax);
+}
+
+/* alpha for a single-stage update with Courant number mu (0 <= mu <= 1/2).
+ * The new value of cell j is f_j - mu (fhat_{j+1/2} - fhat_{j-1/2}).  On
+ * monotone data, with fhat_{j-1/2} between f_{j-1} and f_j and fhat_{j+1/2}
+ * between f_j and f_j + alpha (f_j - f_{j-1}), it stays between f_{j-1} and
+ * f_j as long as mu (1 + alpha) <= 1: the largest such alpha is (1-mu)/mu
+ * (Suresh and Huynh's fixed alpha = 4 is this bound at mu = 0.2, the
+ * Courant number their Runge-Kutta stages allow).  The split of the shift
+ * keeps mu <= 1/2, so alpha >= 1.  Below mu = 1/(1 + 2^20) alpha stays at
+ * 2^20: the bound remains finite at a whole-cell shift, and any smaller
+ * alpha keeps the property. */
+double vor_mp_alpha(double mu)
+{
+    const double cap = VOR_ALPHA_CAP;
+    if (mu * (cap + 1.0) <= 1.0) return cap;
+    return (1.0 - mu) / mu;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -131,11 +151,16 @@ static double ext(const double* f, long M, long j, int periodic)
     return (j >= 0 && j < M) ? f[j] : 0.0;
 }
 
-/* Split a shift s (in cells) into an integer part N and a fraction nu with  */
-/* nu in [0,1) for s >= 0 and nu in (-1,0] for s < 0.                        */
+/* Split a shift s (in cells) into the nearest integer N (halves rounded    */
+/* away from zero) and a fraction nu = s - N with |nu| <= 1/2: the integer   */
+/* part is an exact translation and the fraction, at most half a cell either */
+/* way, goes through the flux.  (Splitting at the floor instead leaves       */
+/* fractions up to a whole cell, where the bounds of vor_mp5_limit cannot    */
+/* keep the update monotone: the fixed 1/2 of f_LC exceeds (1-mu)/mu above   */
+/* mu = 2/3.)                                                                */
 void vor_split_shift(double s, long* N, double* nu)
 {
-    double n = (s >= 0.0) ? floor(s) : ceil(s);
+    double n = round(s);
     *N = (long)n;
     *nu = s - n;
 }
@@ -164,7 +189,7 @@ double vor_interface_flux(const double* f, long M, long j, double nu, int period
     }
     vor_sl5_weights(mu, w);
     fhat = w[0] * a + w[1] * b + w[2] * c + w[3] * d + w[4] * e;
-    lim = limiter ? vor_mp5_limit(fhat, a, b, c, d, e) : fhat;
+    lim = limiter ? vor_mp5_limit(fhat, a, b, c, d, e, vor_mp_alpha(mu)) : fhat;
     /* positivity: the mass leaving the upwind cell lies between 0 and the
      * content of that cell */
     phi = vor_median3(mu * lim, 0.0, c);

@@ -22,7 +22,10 @@ typedef struct {
 double vor_median3(double x, double y, double z);
 double vor_minmod4(double w, double x, double y, double z);
 void vor_sl5_weights(double mu, double w[5]);
-double vor_mp5_limit(double fhat, double a, double b, double c, double d, double e);
+/* largest alpha of the upper limit used by the bounds (see vor_mp_alpha) */
+#define VOR_ALPHA_CAP 1048576.0
+double vor_mp5_limit(double fhat, double a, double b, double c, double d, double e, double alpha);
+double vor_mp_alpha(double mu);
 void vor_split_shift(double s, long* N, double* nu);
 double vor_interface_flux(const double* f, long M, long j, double nu, int periodic, int limiter);
 void vor_sweep_line_opt(const double* f, double* out, long M, double s, int periodic,

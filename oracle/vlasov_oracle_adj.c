@@ -11,7 +11,9 @@
  * and the column df'/dnu by evaluating the forward formulas of
  * vlasov_oracle.c on dual numbers (value, gradient with respect to the five
  * stencil values, derivative with respect to the fraction).  Tangents are
- * J v + (df'/dnu) dnu; adjoints are J^T lambda and lambda . df'/dnu.
+ * J v + (df'/dnu) dnu; adjoints are J^T lambda and lambda . df'/dnu.  The
+ * fraction enters through the weights, the factor mu of the flux and the
+ * alpha(mu) of the bounds' upper limit.
  *
  * Selection rule at ties (equal values, where the derivative is not unique):
  * min and max keep their first argument, the median is max(min(x,y),
@@ -115,13 +117,15 @@ static dual dflux(const double x[5], double mu, int limiter)
     for (int k = 0; k < 5; ++k) fhat = dadd(fhat, dmul_mu(w[k], st[k]));
     dual lim = fhat;
     if (limiter) {
-        const double alpha = 4.0;
+        /* alpha(mu) of vor_mp_alpha with its derivative -1/mu^2 (0 where capped) */
+        dual alpha = dconst(vor_mp_alpha(mu));
+        if (mu * (VOR_ALPHA_CAP + 1.0) > 1.0) alpha.dmu = -1.0 / (mu * mu);
         dual Dm = dadd(dsub(a, dscale(2.0, b)), c);
         dual D0 = dadd(dsub(b, dscale(2.0, c)), d);
         dual Dp = dadd(dsub(c, dscale(2.0, d)), e);
         dual dM4p = dminmod4(dsub(dscale(4.0, D0), Dp), dsub(dscale(4.0, Dp), D0), D0, Dp);
         dual dM4m = dminmod4(dsub(dscale(4.0, D0), Dm), dsub(dscale(4.0, Dm), D0), D0, Dm);
-        dual fUL = dadd(c, dscale(alpha, dsub(c, b)));
+        dual fUL = dadd(c, dmul_mu(alpha, dsub(c, b)));
         dual fAV = dscale(0.5, dadd(c, d));
         dual fMD = dsub(fAV, dscale(0.5, dM4p));
         dual fLC = dadd(dadd(c, dscale(0.5, dsub(c, b))), dscale(4.0 / 3.0, dM4m));
@@ -155,11 +159,12 @@ void vor_sweep_line_jacobian(const double* f, long M, double s, int periodic, in
     memset(J, 0, sizeof(double) * M * M);
     memset(dnu, 0, sizeof(double) * M);
     const double mu = fabs(nu);
-    /* The upwind side follows the sign of s; at a whole-cell shift (nu = 0)
-     * the flux vanishes and its derivative is the one-sided limit from that
-     * side (the flux is mu times the limited value, and a tie between that
-     * product and 0 in the clamp keeps the product). */
-    const int neg = s < 0.0;
+    /* The upwind side follows the sign of nu; at a whole-cell shift (nu = 0)
+     * the flux vanishes and its derivative is the one-sided limit from the
+     * side of s's sign, i.e. for a growing |s| (the flux is mu times the
+     * limited value, and a tie between that product and 0 in the clamp keeps
+     * the product). */
+    const int neg = nu < 0.0 || (nu == 0.0 && s < 0.0);
     for (long i = 0; i < M; ++i) {
         long j = i - N;
         long src = wrap_or_drop(j, M, periodic);
