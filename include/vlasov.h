@@ -11,8 +11,13 @@
  *   - each 1D operator is SL-MPP5 (section 5.2): fifth-order finite volume,
  *     conservative semi-Lagrangian interface flux (exact integral of the
  *     quartic reconstruction over the upwind departure interval), limited by
- *     the Suresh-Huynh monotonicity-preserving bounds (alpha = 4) and a
- *     positivity clamp, one flux evaluation per cell per step;
+ *     the Suresh-Huynh monotonicity-preserving bounds and a positivity
+ *     clamp, one flux evaluation per cell per step.  The shift s splits
+ *     into its nearest integer (an exact translation) and a fraction nu of
+ *     at most half a cell; the bounds' upper limit f_j + alpha (f_j - f_{j-1})
+ *     takes alpha = (1-|nu|)/|nu|, the largest value for which the
+ *     single-stage update keeps monotone data monotone, so repeated sweeps
+ *     create no new extrema at any shift;
  *   - FP32 flux arithmetic (section 5.1.1); FP64 only for reductions;
  *   - velocity moments per spatial cell without data exchange (5.1.3).
  *
@@ -103,7 +108,8 @@ size_t vlasov_scale_bytes(const vlasov_grid* grid, vlasov_prec prec);
  * the line with velocity index j is s_j = u_j * dt_over_a2 / dx in cells
  * (dt_over_a2 = dt / a(t)^2; a = 1 gives dt).  s = N + nu is split into an
  * integer part applied as an exact translation and a fraction applied by the
- * SL-MPP5 flux; the box is periodic.  Any |s| is accepted.
+ * SL-MPP5 flux (see the method summary above); the box is periodic.  Any
+ * |s| is accepted.
  *   f_in / scale_in : input f (and its scales for F16/BF16)
  *   f_out / scale_out : output f (and scales); must not overlap the inputs
  */
@@ -413,6 +419,28 @@ int vlasov_step_adj(const vlasov_grid* grid, vlasov_vbc vbc, const float* f_in,
 int vlasov_moments_adj(const vlasov_grid* grid, const double* rho, const double* umean,
                        const double* lam_rho, const double* lam_umean, float* lam_f,
                        void* stream);
+
+/*
+ * Storage codec of the FP16/BF16 forms (the reduced-precision storage of f;
+ * the paper's own arithmetic, section 5.1.1, is FP32 throughout).
+ *   vlasov_encode: f32 (FP32, layout of f) -> codes (layout of f, 2 bytes
+ *     each) and scale ([nx][ny][nz][nux][nuy] FP32): scale = the largest
+ *     |value| of the uz-line, code = RNE(value * r) with r the hardware
+ *     reciprocal of the scale (0 for an all-zero line) -- exactly what every
+ *     sweep stores for the same FP32 values.
+ *   vlasov_decode: codes, scale -> f32 = code * scale in FP32, exactly what
+ *     every sweep loads.
+ * With VLASOV_F32 both copy the values (scale unused, may be NULL).  Device
+ * pointers, caller-owned; codes and f32 16-byte aligned; nu_z a power of two
+ * from 4 to 64 for FP16/BF16.  Errors: VLASOV_ERR_NULL (grid, f32 or codes
+ * NULL), VLASOV_ERR_PREC (unknown precision; FP16/BF16 without scale),
+ * VLASOV_ERR_SHAPE (grid, alignment or nu_z), VLASOV_ERR_ALIAS (outputs
+ * overlap inputs), VLASOV_ERR_DEVICE.
+ */
+int vlasov_encode(const vlasov_grid* grid, vlasov_prec prec, const float* f32, void* codes,
+                  float* scale, void* stream);
+int vlasov_decode(const vlasov_grid* grid, vlasov_prec prec, const void* codes,
+                  const float* scale, float* f32, void* stream);
 
 /* Deterministic FP64 sum of x[0..n) into *out (device pointers): a single
  * work-group, fixed order.  Used for total mass and total outflow. */

@@ -51,16 +51,24 @@ __device__ __forceinline__ WeightSlopes sl5_weight_slopes(float mu)
     return s;
 }
 
-// Linear form over the stencil (a, b, c, d, e).
+// Linear form over the stencil (a, b, c, d, e), with the derivative with
+// respect to mu in slot 5 (the stencil values do not depend on mu).
 struct Lin {
-    float w[5];
+    float w[6];
 };
 
-__device__ __forceinline__ Lin lin_unit(int k)
+__device__ __forceinline__ Lin lin_zero()
 {
     Lin r;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) r.w[q] = q == k ? 1.0f : 0.0f;
+    for (int q = 0; q < 6; ++q) r.w[q] = 0.0f;
+    return r;
+}
+
+__device__ __forceinline__ Lin lin_unit(int k)
+{
+    Lin r = lin_zero();
+    r.w[k] = 1.0f;
     return r;
 }
 
@@ -68,7 +76,7 @@ __device__ __forceinline__ Lin lin_comb(float p, const Lin& x, float q, const Li
 {
     Lin r;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) r.w[i] = p * x.w[i] + q * y.w[i];
+    for (int i = 0; i < 6; ++i) r.w[i] = p * x.w[i] + q * y.w[i];
     return r;
 }
 
@@ -89,10 +97,7 @@ __device__ __forceinline__ VL vminmod4(const VL& w, const VL& x, const VL& y, co
         return vmin2(vmin2(w, x), vmin2(y, z));
     if (w.v < 0.0f && x.v < 0.0f && y.v < 0.0f && z.v < 0.0f)
         return vmax2(vmax2(w, x), vmax2(y, z));
-    VL r;
-    r.v = 0.0f;
-    r.l = lin_comb(0.0f, lin_unit(0), 0.0f, lin_unit(0));
-    return r;
+    return VL{0.0f, lin_zero()};
 }
 
 struct FluxLin {
@@ -101,68 +106,108 @@ struct FluxLin {
     float dmu;      // d phi / d mu
 };
 
+// mp_bounded on (value, form) pairs: the values with mp_bounded's FP32
+// operations, so every selection is the forward's.  u[] are the forms of the
+// stencil's a..e (the upwind frame's cells, or mirrored for a comp line);
+// the upper-limit factor alpha carries its mu-derivative alpha_mu.
+__device__ VL mp_bounded_lin(const VL& fhat, const Stencil& s, const Lin (&u)[5], float alpha,
+                             float alpha_mu)
+{
+    const float Dmv = s.dm1 - s.dm2, D0v = s.d0 - s.dm1, Dpv = s.dp1 - s.d0;
+    const Lin cb = lin_comb(1.0f, u[2], -1.0f, u[1]);                       // c - b
+    const VL Dm{Dmv, lin_comb(1.0f, lin_comb(1.0f, u[0], -2.0f, u[1]), 1.0f, u[2])};
+    const VL D0{D0v, lin_comb(1.0f, lin_comb(1.0f, u[1], -2.0f, u[2]), 1.0f, u[3])};
+    const VL Dp{Dpv, lin_comb(1.0f, lin_comb(1.0f, u[2], -2.0f, u[3]), 1.0f, u[4])};
+    // curv_minmod(Da, Db) = minmod(4Da-Db, 4Db-Da, Da, Db)
+    const VL p1{fmaf(4.0f, D0v, -Dpv), lin_comb(4.0f, D0.l, -1.0f, Dp.l)};
+    const VL q1{fmaf(4.0f, Dpv, -D0v), lin_comb(4.0f, Dp.l, -1.0f, D0.l)};
+    const VL Mp = vminmod4(p1, q1, D0, Dp);
+    const VL p2{fmaf(4.0f, Dmv, -D0v), lin_comb(4.0f, Dm.l, -1.0f, D0.l)};
+    const VL q2{fmaf(4.0f, D0v, -Dmv), lin_comb(4.0f, D0.l, -1.0f, Dm.l)};
+    const VL Mm = vminmod4(p2, q2, Dm, D0);
+    const VL c{s.c, u[2]};
+    const VL d{s.d, u[3]};
+    VL fUL{fmaf(alpha, s.dm1, s.c), lin_comb(alpha, cb, 1.0f, u[2])};
+    fUL.l.w[5] += alpha_mu * s.dm1;
+    const VL fMD{0.5f * ((s.c + s.d) - Mp.v),
+                 lin_comb(0.5f, lin_comb(1.0f, u[2], 1.0f, u[3]), -0.5f, Mp.l)};
+    const VL fLC{fmaf(4.0f / 3.0f, Mm.v, fmaf(0.5f, s.dm1, s.c)),
+                 lin_comb(4.0f / 3.0f, Mm.l, 1.0f, lin_comb(0.5f, cb, 1.0f, u[2]))};
+    const VL lo = vmax2(vmin2(vmin2(c, d), fMD), vmin2(vmin2(c, fUL), fLC));
+    const VL hi = vmin2(vmax2(vmax2(c, d), fMD), vmax2(vmax2(c, fUL), fLC));
+    return vmed3(fhat, lo, hi);
+}
+
 // The forward flux with its frozen linearisation.  The values follow
-// flux_mag / mp_bounded operation by operation.
+// flux_mag / mp_flux / mp_bounded operation by operation, so every selection
+// is the forward's (the clamp of a comp line is read on the complement, see
+// below).
 __device__ FluxLin flux_lin(const Stencil& s, const LineShift& sh, const WeightSlopes& ds)
 {
     float y = sh.v0 * s.dm2;
     y = fmaf(sh.v1, s.dm1, y);
     y = fmaf(sh.v2, s.d0, y);
     y = fmaf(sh.v3, s.dp1, y);
-    const float m = med3(s.d0, 4.0f * s.dm1, 0.0f);
-    VL L;
-    L.v = s.c + y;
-    L.l.w[0] = sh.w0; L.l.w[1] = sh.w1; L.l.w[2] = sh.w2; L.l.w[3] = sh.w3; L.l.w[4] = sh.w4;
-    bool L_is_fhat = true;
-    if (med3(y, 0.0f, m) != y) {
-        // curvatures as differences of differences (as in mp_bounded)
-        const float Dmv = s.dm1 - s.dm2, D0v = s.d0 - s.dm1, Dpv = s.dp1 - s.d0;
-        VL Dm{Dmv, {{1.0f, -2.0f, 1.0f, 0.0f, 0.0f}}};
-        VL D0{D0v, {{0.0f, 1.0f, -2.0f, 1.0f, 0.0f}}};
-        VL Dp{Dpv, {{0.0f, 0.0f, 1.0f, -2.0f, 1.0f}}};
-        // curv_minmod(Da, Db) = minmod(4Da-Db, 4Db-Da, Da, Db)
-        VL p1{fmaf(4.0f, D0v, -Dpv), lin_comb(4.0f, D0.l, -1.0f, Dp.l)};
-        VL q1{fmaf(4.0f, Dpv, -D0v), lin_comb(4.0f, Dp.l, -1.0f, D0.l)};
-        const VL Mp = vminmod4(p1, q1, D0, Dp);
-        VL p2{fmaf(4.0f, Dmv, -D0v), lin_comb(4.0f, Dm.l, -1.0f, D0.l)};
-        VL q2{fmaf(4.0f, D0v, -Dmv), lin_comb(4.0f, D0.l, -1.0f, Dm.l)};
-        const VL Mm = vminmod4(p2, q2, Dm, D0);
-        const VL c{s.c, lin_unit(2)};
-        const VL d{s.d, lin_unit(3)};
-        const Lin cb = lin_comb(1.0f, lin_unit(2), -1.0f, lin_unit(1));
-        VL fUL{fmaf(4.0f, s.dm1, s.c), lin_comb(4.0f, cb, 1.0f, c.l)};
-        VL fMD{0.5f * ((s.c + s.d) - Mp.v),
-               lin_comb(0.5f, lin_comb(1.0f, c.l, 1.0f, d.l), -0.5f, Mp.l)};
-        VL fLC{fmaf(4.0f / 3.0f, Mm.v, fmaf(0.5f, s.dm1, s.c)),
-               lin_comb(4.0f / 3.0f, Mm.l, 1.0f, lin_comb(0.5f, cb, 1.0f, c.l))};
-        const VL lo = vmax2(vmin2(vmin2(c, d), fMD), vmin2(vmin2(c, fUL), fLC));
-        const VL hi = vmin2(vmax2(vmax2(c, d), fMD), vmax2(vmax2(c, fUL), fLC));
-        const VL r = vmed3(L, lo, hi);
-        L_is_fhat = r.v == L.v && r.l.w[0] == L.l.w[0] && r.l.w[1] == L.l.w[1] &&
-                    r.l.w[2] == L.l.w[2] && r.l.w[3] == L.l.w[3] && r.l.w[4] == L.l.w[4];
-        L = r;
-    }
-    float Ldmu = 0.0f;
-    if (L_is_fhat) {
-        Ldmu = ds.d0 * s.a;
-        Ldmu = fmaf(ds.d1, s.b, Ldmu);
-        Ldmu = fmaf(ds.d2, s.c, Ldmu);
-        Ldmu = fmaf(ds.d3, s.d, Ldmu);
-        Ldmu = fmaf(ds.d4, s.e, Ldmu);
-    }
-    // positivity clamp med3(mu L, 0, c), oracle tie rules
-    const float x = sh.mu * L.v;
-    VL X{x, lin_comb(sh.mu, L.l, 0.0f, L.l)};
-    VL Z{0.0f, lin_comb(0.0f, L.l, 0.0f, L.l)};
-    VL C{s.c, lin_unit(2)};
-    const VL r = vmed3(X, Z, C);
+    const float m = med3(s.d0, sh.alpha * s.dm1, 0.0f);
+    // y = fhat - c as a form: the weights, and d fhat / d mu
+    VL Y;
+    Y.v = y;
+    Y.l.w[0] = sh.w0; Y.l.w[1] = sh.w1; Y.l.w[2] = sh.w2 - 1.0f; Y.l.w[3] = sh.w3;
+    Y.l.w[4] = sh.w4;
+    float ydmu = ds.d0 * s.a;
+    ydmu = fmaf(ds.d1, s.b, ydmu);
+    ydmu = fmaf(ds.d2, s.c, ydmu);
+    ydmu = fmaf(ds.d3, s.d, ydmu);
+    ydmu = fmaf(ds.d4, s.e, ydmu);
+    Y.l.w[5] = ydmu;
+    const Lin uc = lin_unit(2);
+    const bool early = med3(y, 0.0f, m) == y;
+    const VL zero{0.0f, lin_zero()};
+    const VL C{s.c, uc};
     FluxLin out;
-    out.phi = r.v;
+    // the value: flux_mag's own operations
+    float pre_v = sh.mu * (s.c + y);
+    if (!early) pre_v = mp_flux(s, sh, y);
+    out.phi = med3(pre_v, 0.0f, s.c);
+    VL r;
+    if (!sh.comp) {
+        VL F{s.c + y, lin_comb(1.0f, uc, 1.0f, Y.l)};
+        if (!early) {
+            // d alpha / d mu = -1/mu^2 (0 where alpha is held at its cap)
+            const float a_mu = sh.mu * (kAlphaCap + 1.0f) <= 1.0f ? 0.0f : -1.0f / (sh.mu * sh.mu);
+            const Lin u[5] = {lin_unit(0), lin_unit(1), lin_unit(2), lin_unit(3), lin_unit(4)};
+            F = mp_bounded_lin(F, s, u, sh.alpha, a_mu);
+        }
+        // positivity clamp med3(mu L, 0, c), oracle tie rules
+        VL pre{sh.mu * F.v, lin_comb(sh.mu, F.l, 0.0f, F.l)};
+        pre.l.w[5] = fmaf(sh.mu, F.l.w[5], F.v);
+        r = vmed3(pre, zero, C);
+    } else {
+        // complement: ghat = c - q y on the mirrored stencil with alpha_c; what
+        // leaves through the complement side is Psi = med3(mu' ghat_lim, 0, c)
+        // and Phi = c - Psi.  The selections of that clamp are taken on Psi,
+        // as the split at the nearest integer takes them (its tie rules differ
+        // from those of the same clamp written on Phi where c = 0).
+        // dq/dmu = 1/mu'^2, d alpha_c/dmu = 1/mu'^2 (0 where held at its cap),
+        // dmu'/dmu = -1.
+        const float q_mu = 1.0f / (sh.muc * sh.muc);
+        VL G{fmaf(-sh.q, y, s.c), lin_comb(1.0f, uc, -sh.q, Y.l)};
+        G.l.w[5] = -sh.q * Y.l.w[5] - q_mu * y;
+        if (!early) {
+            const float ac_mu = sh.muc * (kAlphaCap + 1.0f) <= 1.0f ? 0.0f : q_mu;
+            const Stencil mst{s.e, s.d, s.c, s.b, s.a, -s.dp1, -s.d0, -s.dm1, -s.dm2};
+            const Lin u[5] = {lin_unit(4), lin_unit(3), lin_unit(2), lin_unit(1), lin_unit(0)};
+            G = mp_bounded_lin(G, mst, u, sh.alpha_c, ac_mu);
+        }
+        VL P{sh.muc * G.v, lin_comb(sh.muc, G.l, 0.0f, G.l)};
+        P.l.w[5] = sh.muc * G.l.w[5] - G.v;
+        const VL psi = vmed3(P, zero, C);
+        r.v = s.c - psi.v;
+        r.l = lin_comb(1.0f, uc, -1.0f, psi.l);
+    }
 #pragma unroll
     for (int q = 0; q < 5; ++q) out.W[q] = r.l.w[q];
-    const bool took_x = r.v == X.v && r.l.w[0] == X.l.w[0] && r.l.w[1] == X.l.w[1] &&
-                        r.l.w[2] == X.l.w[2] && r.l.w[3] == X.l.w[3] && r.l.w[4] == X.l.w[4];
-    out.dmu = took_x ? fmaf(sh.mu, Ldmu, L.v) : 0.0f;
+    out.dmu = r.l.w[5];
     return out;
 }
 

@@ -925,6 +925,47 @@ int vlasov_moments_adj(const vlasov_grid* g, const double* rho, const double* um
     return from_hip(launch_moments_adj(a, lam_rho, lam_umean, lam_f, (hipStream_t)stream));
 }
 
+static int codec_args(const vlasov_grid* g, vlasov_prec prec, const void* f32, const void* codes,
+                      const void* scale, Dims& d)
+{
+    if (g == nullptr || f32 == nullptr || codes == nullptr) return VLASOV_ERR_NULL;
+    if (!dims_of(g, d)) return VLASOV_ERR_SHAPE;
+    if (!prec_ok(prec)) return VLASOV_ERR_PREC;
+    if (!aligned16(f32) || !aligned16(codes)) return VLASOV_ERR_SHAPE;
+    const size_t fb = (size_t)d.total * 4, cb = (size_t)d.total * elem_bytes(prec);
+    if (overlap(f32, fb, codes, cb)) return VLASOV_ERR_ALIAS;
+    if (prec == VLASOV_F32) return VLASOV_OK;
+    if (scale == nullptr) return VLASOV_ERR_PREC;
+    if (!scaled_shape_ok(d)) return VLASOV_ERR_SHAPE;
+    const size_t sb = (size_t)(d.total / d.nu[2]) * sizeof(float);
+    if (overlap(scale, sb, f32, fb) || overlap(scale, sb, codes, cb)) return VLASOV_ERR_ALIAS;
+    return VLASOV_OK;
+}
+
+int vlasov_encode(const vlasov_grid* g, vlasov_prec prec, const float* f32, void* codes,
+                  float* scale, void* stream)
+{
+    Dims d;
+    const int rc = codec_args(g, prec, f32, codes, scale, d);
+    if (rc) return rc;
+    if (prec == VLASOV_F32)
+        return from_hip(hipMemcpyAsync(codes, f32, (size_t)d.total * 4, hipMemcpyDeviceToDevice,
+                                       (hipStream_t)stream));
+    return from_hip(launch_encode(prec, f32, codes, scale, d.total, d.nu[2], (hipStream_t)stream));
+}
+
+int vlasov_decode(const vlasov_grid* g, vlasov_prec prec, const void* codes, const float* scale,
+                  float* f32, void* stream)
+{
+    Dims d;
+    const int rc = codec_args(g, prec, f32, codes, scale, d);
+    if (rc) return rc;
+    if (prec == VLASOV_F32)
+        return from_hip(hipMemcpyAsync(f32, codes, (size_t)d.total * 4, hipMemcpyDeviceToDevice,
+                                       (hipStream_t)stream));
+    return from_hip(launch_decode(prec, codes, scale, f32, d.total, d.nu[2], (hipStream_t)stream));
+}
+
 int vlasov_sum_f64(const double* x, int64_t n, double* out, void* stream)
 {
     if (x == nullptr || out == nullptr) return VLASOV_ERR_NULL;

@@ -178,9 +178,11 @@ __device__ __forceinline__ float kick_axis(float* lds, float* sout_line, float* 
         // scalar loads of the precomputed split (uniform over the work-group)
         const KickShift e = tab[(long)cell * 3 + AXIS];
         sh.N = e.N;
-        sh.neg = e.neg != 0;
+        sh.neg = (e.flags & 1) != 0;
+        sh.comp = (e.flags & 2) != 0;
         sh.mu = e.mu;
         sh.v0 = e.v0; sh.v1 = e.v1; sh.v2 = e.v2; sh.v3 = e.v3;
+        sh.alpha = e.alpha; sh.q = e.q; sh.alpha_c = e.alpha_c; sh.muc = e.muc;
     } else {
         sh = split_shift((double)g * a.factor[AXIS], NU, PER);
     }
@@ -414,9 +416,10 @@ __global__ void __launch_bounds__(256) k_kick_shifts(KickArgs a, KickShift* __re
                                      a.nu[axis], a.periodic);
     KickShift e;
     e.N = sh.N;
-    e.neg = sh.neg ? 1 : 0;
+    e.flags = (sh.neg ? 1 : 0) | (sh.comp ? 2 : 0);
     e.mu = sh.mu;
     e.v0 = sh.v0; e.v1 = sh.v1; e.v2 = sh.v2; e.v3 = sh.v3;
+    e.alpha = sh.alpha; e.q = sh.q; e.alpha_c = sh.alpha_c; e.muc = sh.muc;
     e.pad = 0.0f;
     tab[i] = e;
 }

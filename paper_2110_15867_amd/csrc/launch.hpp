@@ -48,13 +48,15 @@ hipError_t launch_vel_uz(int prec, const void* fin, const float* sin, void* fout
                          const VelArgs& a, hipStream_t st);
 
 // Split shift of one velocity line (uniform over a spatial cell's block):
-// integer part, direction and the fractional part's interface weights in
-// difference form; precomputed per cell and axis for the fused kick.
+// integer part, direction, the fractional part's interface weights in
+// difference form and the limiter constants (LineShift); precomputed per
+// cell and axis for the fused kick.
 struct KickShift {
     int N;
-    int neg;
+    int flags;       // bit 0: walked mirrored (neg), bit 1: complement bounds (comp)
     float mu;
     float v0, v1, v2, v3;
+    float alpha, q, alpha_c, muc;
     float pad;
 };
 
@@ -93,6 +95,13 @@ struct MomArgs {
 hipError_t launch_moments(int prec, const void* f, const float* scale, const MomArgs& a,
                           hipStream_t st);
 hipError_t launch_sum(const double* x, long n, double scale, double* out, hipStream_t st);
+
+// Storage codec (FP16/BF16 codes + per-uz-line scale); total values, uz-line
+// length nuz (a power of two from 4 to 64)
+hipError_t launch_encode(int prec, const float* f, void* codes, float* scale, long total, long nuz,
+                         hipStream_t st);
+hipError_t launch_decode(int prec, const void* codes, const float* scale, float* f, long total,
+                         long nuz, hipStream_t st);
 
 // Field of a density on the periodic mesh (Eq. 2), FP64 DFTs.
 struct FieldArgs {

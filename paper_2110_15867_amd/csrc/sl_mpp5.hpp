@@ -62,11 +62,14 @@ __device__ __forceinline__ float uniform_f32(float v)
     return __builtin_bit_cast(float, uniform_sgpr(__builtin_bit_cast(int, v)));
 }
 
-// Inverse of a line scale (0 for an all-zero line): the hardware reciprocal,
-// used by every kernel that encodes, so all of them produce the same codes.
+// Inverse of a line scale: the hardware reciprocal, used by every kernel that
+// encodes, so all of them produce the same codes.  A line whose largest
+// |value| is below the smallest normal FP32 number (1.2e-38) is stored as
+// zeros, as an all-zero line is: the reciprocal of such a scale overflows
+// FP32 (a finite value times it would give an infinite code, a zero a NaN).
 __device__ __forceinline__ float inv_scale(float m)
 {
-    return m > 0.0f ? __builtin_amdgcn_rcpf(m) : 0.0f;
+    return m >= 1.17549435e-38f ? __builtin_amdgcn_rcpf(m) : 0.0f;
 }
 
 // Code of value x with inverse scale inv: the FP32 product, rounded once to
@@ -107,14 +110,45 @@ __device__ __forceinline__ void store_row(typename Codec<P>::T* p, const float* 
 // (-1,0] for s < 0 (Eqs. 3-4 give s; the integer part is an exact
 // translation).  Everything after the split runs in the upwind frame, where
 // the shift is non-negative: `neg` says the line is walked mirrored.
+//
+// The limiter's reading splits the shift at the nearest integer instead, so
+// that the fraction is at most half a cell either way and the Suresh-Huynh
+// upper limit f_j + alpha (f_j - f_{j-1}) can use alpha = (1-|nu|)/|nu|, the
+// largest value for which a single-stage update keeps monotone data
+// monotone.  For a fraction mu >= 1/2 of the floor split that is the
+// translation by N+1 followed by a move back by mu' = 1 - mu.  Both give the
+// same unlimited flux through x_{j+1/2}: the quartic of cell j integrated
+// over the last mu of the cell is the cell's content minus the quartic
+// integrated over its first mu', so Phi = mu fhat = f_j - mu' ghat, where
+// ghat is the mirrored interface value of the first mu' of cell j, and
+// ghat - f_j = -(mu/mu') (fhat - f_j).  Such a line is flagged `comp`
+// (complement): its bounds are those of ghat on the mirrored stencil with
+// alpha' = alpha(mu'), and its flux is f_j - mu' ghat_lim.  The Suresh-Huynh
+// early-out needs no change: with alpha = mu'/mu the interval test on
+// fhat - f_j is the mirrored test on ghat - f_j with alpha' = mu/mu' (where
+// alpha' is held at its cap the two tests differ, and such lines always
+// evaluate the bounds).
 // ---------------------------------------------------------------------------
 struct LineShift {
     int N;      // integer part in the upwind frame (>= 0), reduced mod M when periodic
     float mu;   // fractional part |nu| in [0,1)
     bool neg;   // s < 0: walk the line mirrored
+    bool comp;  // |nu| >= 1/2: the bounds act on the complement (see above)
+    float alpha;                // upper-limit factor of the early-out test (and of the
+                                // bounds of a line that is not comp), alpha(mu)
+    float q, alpha_c, muc;      // comp lines: mu/mu', alpha(mu'), mu' = 1 - mu
     float w0, w1, w2, w3, w4;   // interface-value weights for cells j-2 .. j+2
     float v0, v1, v2, v3;       // the same in difference form (see sl5_weights)
 };
+
+// Largest upper-limit factor of a single-stage update with Courant number
+// mu: (1-mu)/mu, held at 2^20 below mu = 1/(1+2^20) so that it stays finite
+// at a whole-cell shift (a smaller factor keeps the property).
+constexpr float kAlphaCap = 1048576.0f;
+__device__ __forceinline__ float mp_alpha(float mu)
+{
+    return mu * (kAlphaCap + 1.0f) <= 1.0f ? kAlphaCap : (1.0f - mu) / mu;
+}
 
 // Interface value of the conservative SL flux: the mean over the departure
 // interval of the quartic through the five cell averages j-2..j+2.  The flux
@@ -139,6 +173,25 @@ __device__ __forceinline__ void sl5_weights(float mu, LineShift& sh)
     sh.v3 = sh.w4;
 }
 
+// The limiter constants of the fraction nu (FP64; mu = |nu| in FP32).  For a
+// comp line mu' is taken from FP64, where 1 - |nu| is exact and positive
+// (mu itself may round to 1 in FP32).
+__device__ __forceinline__ void mp_params(double nu, float mu, LineShift& sh)
+{
+    sh.comp = fabs(nu) >= 0.5;
+    if (!sh.comp) {
+        sh.alpha = mp_alpha(mu);
+        sh.q = 0.0f;
+        sh.alpha_c = 0.0f;
+        sh.muc = 0.0f;
+        return;
+    }
+    sh.muc = (float)(1.0 - fabs(nu));
+    sh.q = mu / sh.muc;
+    sh.alpha_c = mp_alpha(sh.muc);
+    sh.alpha = sh.muc * (kAlphaCap + 1.0f) <= 1.0f ? 0.0f : sh.muc / mu;
+}
+
 __device__ __forceinline__ LineShift split_shift(double s, int M, bool periodic)
 {
     LineShift sh;
@@ -154,13 +207,14 @@ __device__ __forceinline__ LineShift split_shift(double s, int M, bool periodic)
     sh.N = (int)a;
     sh.mu = (float)fabs(nu);
     sl5_weights(sh.mu, sh);
+    mp_params(nu, sh.mu, sh);
     return sh;
 }
 
 // ---------------------------------------------------------------------------
-// Suresh-Huynh monotonicity-preserving bounds (alpha = 4, epsilon = 0) and the
-// positivity clamp, for one interface in its upwind frame; a..e are the cell
-// averages j-2..j+2 (j = upwind cell).
+// Suresh-Huynh monotonicity-preserving bounds (epsilon = 0, upper-limit
+// factor alpha) and the positivity clamp, for one interface in its upwind
+// frame; a..e are the cell averages j-2..j+2 (j = upwind cell).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float med3(float a, float b, float c)
 {
@@ -192,19 +246,32 @@ struct Stencil {
 };
 
 // The bounded value median(fhat, fmin, fmax) of the Suresh-Huynh constraint.
-__device__ __forceinline__ float mp_bounded(float fhat, const Stencil& s)
+__device__ __forceinline__ float mp_bounded(float fhat, const Stencil& s, float alpha)
 {
     const float Dm = s.dm1 - s.dm2;                 // curvature at j-1
     const float D0 = s.d0 - s.dm1;                  // curvature at j
     const float Dp = s.dp1 - s.d0;                  // curvature at j+1
     const float Mp = curv_minmod(D0, Dp);           // d^M4 at j+1/2
     const float Mm = curv_minmod(Dm, D0);           // d^M4 at j-1/2
-    const float fUL = fmaf(4.0f, s.dm1, s.c);
+    const float fUL = fmaf(alpha, s.dm1, s.c);
     const float fMD = 0.5f * ((s.c + s.d) - Mp);
     const float fLC = fmaf(4.0f / 3.0f, Mm, fmaf(0.5f, s.dm1, s.c));
     const float lo = fmaxf(fminf(fminf(s.c, s.d), fMD), fminf(fminf(s.c, fUL), fLC));
     const float hi = fminf(fmaxf(fmaxf(s.c, s.d), fMD), fmaxf(fmaxf(s.c, fUL), fLC));
     return med3(fhat, lo, hi);
+}
+
+// Flux (before the positivity clamp) of an interface whose unlimited value
+// fails the Suresh-Huynh test.  comp lines bound the complement ghat on the
+// mirrored stencil (e, d, c, b, a) and return f_j - mu' ghat_lim (see
+// LineShift); the flag is uniform over a line, so a wave whose lanes share
+// the shift takes one branch.
+__device__ __forceinline__ float mp_flux(const Stencil& s, const LineShift& sh, float y)
+{
+    if (!sh.comp) return sh.mu * mp_bounded(s.c + y, s, sh.alpha);
+    const Stencil m{s.e, s.d, s.c, s.b, s.a, -s.dp1, -s.d0, -s.dm1, -s.dm2};
+    const float ghat = fmaf(-sh.q, y, s.c);
+    return fmaf(-sh.muc, mp_bounded(ghat, m, sh.alpha_c), s.c);
 }
 
 // Flux magnitude through the interface j+1/2 in its upwind frame: the SL
@@ -223,11 +290,11 @@ __device__ __forceinline__ float flux_mag(const Stencil& s, const LineShift& sh)
     y = fmaf(sh.v1, s.dm1, y);
     y = fmaf(sh.v2, s.d0, y);
     y = fmaf(sh.v3, s.dp1, y);
-    const float m = med3(s.d0, 4.0f * s.dm1, 0.0f);     // f_MP - f_j
-    float lim = s.c + y;
-    if (__builtin_expect(med3(y, 0.0f, m) != y, 0)) lim = mp_bounded(lim, s);
+    const float m = med3(s.d0, sh.alpha * s.dm1, 0.0f); // f_MP - f_j
+    float pre = sh.mu * (s.c + y);
+    if (__builtin_expect(med3(y, 0.0f, m) != y, 0)) pre = mp_flux(s, sh, y);
     // positivity: what leaves the upwind cell lies between 0 and its content
-    return med3(sh.mu * lim, 0.0f, s.c);
+    return med3(pre, 0.0f, s.c);
 }
 
 // ---------------------------------------------------------------------------

@@ -111,6 +111,10 @@ def _load():
     L.vlasov_sum_f64.argtypes = [P, ctypes.c_int64, P, P]
     L.vlasov_stream_copy.restype = I
     L.vlasov_stream_copy.argtypes = [P, P, S, P]
+    L.vlasov_encode.restype = I
+    L.vlasov_encode.argtypes = [G, I, P, P, P, P]
+    L.vlasov_decode.restype = I
+    L.vlasov_decode.argtypes = [G, I, P, P, P, P]
     _bind_adjoint(L)
     return L
 
@@ -327,6 +331,16 @@ def vlasov_sum_f64(x, n, out, stream=None):
     _check(_lib.vlasov_sum_f64(_ptr(x), int(n), _ptr(out), _stream(stream)), "vlasov_sum_f64")
 
 
+def vlasov_encode(grid, prec, f32, codes, scale, stream=None):
+    _check(_lib.vlasov_encode(ctypes.byref(grid), int(prec), _ptr(f32), _ptr(codes), _ptr(scale),
+                              _stream(stream)), "vlasov_encode")
+
+
+def vlasov_decode(grid, prec, codes, scale, f32, stream=None):
+    _check(_lib.vlasov_decode(ctypes.byref(grid), int(prec), _ptr(codes), _ptr(scale), _ptr(f32),
+                              _stream(stream)), "vlasov_decode")
+
+
 def vlasov_stream_copy(src, dst, nbytes, stream=None):
     _check(_lib.vlasov_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)),
            "vlasov_stream_copy")
@@ -410,24 +424,24 @@ def empty_state(grid, prec, device="cuda") -> State:
     return State(grid, prec, f, scale)
 
 
-def encode(grid, prec, f32) -> State:
-    """Store an FP32 tensor in the given precision (per-uz-line max scale, RNE codes).
-
-    This is input preparation with torch ops; the sweeps themselves requantise
-    inside the kernels.
-    """
+def encode(grid, prec, f32, stream=None) -> State:
+    """Store an FP32 tensor in the given precision through vlasov_encode
+    (per-uz-line max scale, RNE codes: what the sweeps store)."""
+    f32 = f32.contiguous()
     if prec == F32:
-        return State(grid, prec, f32.contiguous())
-    scale = f32.abs().amax(dim=-1).contiguous()
-    inv = torch.where(scale > 0, 1.0 / scale, torch.zeros_like(scale))
-    codes = (f32 * inv[..., None]).to(TORCH_DTYPE[prec]).contiguous()
-    return State(grid, prec, codes, scale)
+        return State(grid, prec, f32)
+    out = empty_state(grid, prec, f32.device)
+    vlasov_encode(grid, prec, f32, out.f, out.scale, stream)
+    return out
 
 
-def decode(state: State) -> torch.Tensor:
+def decode(state: State, stream=None) -> torch.Tensor:
+    """FP32 values of a state through vlasov_decode (code times scale)."""
     if state.prec == F32:
         return state.f
-    return state.f.float() * state.scale[..., None]
+    out = torch.empty(state.f.shape, dtype=torch.float32, device=state.f.device)
+    vlasov_decode(state.grid, state.prec, state.f, state.scale, out, stream)
+    return out
 
 
 def advect(axis: str, state: State, dt, g=None, vbc=VBC_OUTFLOW, outflow=None, stream=None):
