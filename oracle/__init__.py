@@ -103,6 +103,12 @@ def lib():
         D, I, Lg = ctypes.c_double, ctypes.c_int, ctypes.c_long
         L.vor_sweep_line_jacobian.restype = None
         L.vor_sweep_line_jacobian.argtypes = [c_double_p, Lg, D, I, I, c_double_p, c_double_p]
+        L.vor_sweep_line_margin.restype = None
+        L.vor_sweep_line_margin.argtypes = [c_double_p, Lg, D, I, c_double_p]
+        L.vor_advect_position_margin.restype = I
+        L.vor_advect_position_margin.argtypes = [G, I, c_double_p, c_double_p, D]
+        L.vor_advect_velocity_margin.restype = I
+        L.vor_advect_velocity_margin.argtypes = [G, I, I, c_double_p, c_float_p, D, c_double_p]
         L.vor_advect_position_adj.restype = I
         L.vor_advect_position_adj.argtypes = [G, I, c_double_p, c_double_p, c_double_p, D]
         L.vor_advect_velocity_adj.restype = I
@@ -333,6 +339,33 @@ def sweep_line_jacobian(line, s, periodic=True, limiter=True):
     lib().vor_sweep_line_jacobian(_dp(line), M, float(s), int(periodic), int(limiter), _dp(J),
                                   _dp(dn))
     return J, dn
+
+
+def sweep_line_margin(line, s, periodic=True):
+    """Selection margin of every input cell of one line sweep (see vlasov_oracle_adj.c)."""
+    line = _f64(line)
+    out = np.empty_like(line)
+    lib().vor_sweep_line_margin(_dp(line), line.size, float(s), int(periodic), _dp(out))
+    return out
+
+
+def advect_position_margin(grid, axis, f, dt_over_a2):
+    """Per cell: the smallest selection margin of the interfaces that read it (position sweep)."""
+    f = _f64(f)
+    out = np.empty_like(f)
+    _check(lib().vor_advect_position_margin(ctypes.byref(grid), axis, _dp(f), _dp(out),
+                                            dt_over_a2), "advect_position_margin")
+    return out
+
+
+def advect_velocity_margin(grid, axis, f, g, dt, vbc=0):
+    """Per cell: the smallest selection margin of the interfaces that read it (velocity sweep)."""
+    f = _f64(f)
+    g = np.ascontiguousarray(g, dtype=np.float32)
+    out = np.empty_like(f)
+    _check(lib().vor_advect_velocity_margin(ctypes.byref(grid), axis, vbc, _dp(f), _fp(g), dt,
+                                            _dp(out)), "advect_velocity_margin")
+    return out
 
 
 def advect_position_adj(grid, axis, f, lam_out, dt_over_a2):

@@ -51,6 +51,11 @@ void vor_sweep_line_tangent(const double* f, long M, double s, int periodic, con
                             double nu_dot, double* out_dot);
 void vor_sweep_line_adjoint(const double* f, long M, double s, int periodic, const double* lam,
                             double* lam_in, double* lam_nu);
+void vor_sweep_line_margin(const double* f, long M, double s, int periodic, double* margin);
+int vor_advect_position_margin(const vor_grid* g, int a, const double* fin, double* margin,
+                               double dt_over_a2);
+int vor_advect_velocity_margin(const vor_grid* g, int a, int vbc, const double* fin,
+                               const float* gfield, double dt, double* margin);
 int vor_advect_position_adj(const vor_grid* g, int a, const double* fin, const double* lam_out,
                             double* lam_in, double dt_over_a2);
 int vor_advect_velocity_adj(const vor_grid* g, int a, int vbc, const double* fin,

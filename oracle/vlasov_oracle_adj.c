@@ -61,13 +61,57 @@ static dual dlin(double p, dual x, double q, dual y)  /* p x + q y */
 static dual dadd(dual x, dual y) { return dlin(1.0, x, 1.0, y); }
 static dual dsub(dual x, dual y) { return dlin(1.0, x, -1.0, y); }
 static dual dscale(double p, dual x) { return dlin(p, x, 0.0, x); }
-static dual dmin2(dual x, dual y) { return x.v <= y.v ? x : y; }
-static dual dmax2(dual x, dual y) { return x.v >= y.v ? x : y; }
+/* Selection margins.  Every comparison of two values x, y records the gap
+ * |x - y| / max(|x|, |y|, S), S the largest |value| of the interface's
+ * stencil; the smallest gap since the last reset (per thread) tells how
+ * close the interface is to a selection that another rounding of the same
+ * arithmetic (FP32 on the device) could take the other way.  A tie is gap 0
+ * unless both values are exact in any rounding: constants, stencil values,
+ * or combinations of stencil values that are all zero (tl_x holds the
+ * stencil while margins are taken; NULL otherwise, and then nothing is
+ * recorded). */
+static _Thread_local double tl_gap = INFINITY;
+static _Thread_local double tl_scale = 0.0;
+static _Thread_local const double* tl_x = NULL;
+static int exact_in_any_rounding(dual z)
+{
+    int nz = 0, unit = 0;
+    double contrib = 0.0;
+    for (int k = 0; k < 5; ++k) {
+        if (z.g[k] != 0.0) {
+            ++nz;
+            unit = z.g[k] == 1.0;
+            contrib += fabs(z.g[k] * tl_x[k]);
+        }
+    }
+    if (nz == 0) return 1;
+    if (nz == 1 && unit) return 1;
+    return contrib == 0.0;
+}
+static void note_gap(dual x, dual y)
+{
+    if (tl_x == NULL) return;
+    if (x.v == y.v) {
+        if (!(exact_in_any_rounding(x) && exact_in_any_rounding(y))) tl_gap = 0.0;
+        return;
+    }
+    double m = fabs(x.v) > fabs(y.v) ? fabs(x.v) : fabs(y.v);
+    if (tl_scale > m) m = tl_scale;
+    const double g = fabs(x.v - y.v) / m;
+    if (g < tl_gap) tl_gap = g;
+}
+static dual dmin2(dual x, dual y) { note_gap(x, y); return x.v <= y.v ? x : y; }
+static dual dmax2(dual x, dual y) { note_gap(x, y); return x.v >= y.v ? x : y; }
 static dual dmin3(dual x, dual y, dual z) { return dmin2(dmin2(x, y), z); }
 static dual dmax3(dual x, dual y, dual z) { return dmax2(dmax2(x, y), z); }
 static dual dmed3(dual x, dual y, dual z) { return dmax2(dmin2(x, y), dmin2(dmax2(x, y), z)); }
 static dual dminmod4(dual w, dual x, dual y, dual z)
 {
+    const dual zero = dconst(0.0);
+    note_gap(w, zero);
+    note_gap(x, zero);
+    note_gap(y, zero);
+    note_gap(z, zero);
     if (w.v > 0 && x.v > 0 && y.v > 0 && z.v > 0) return dmin2(dmin2(w, x), dmin2(y, z));
     if (w.v < 0 && x.v < 0 && y.v < 0 && z.v < 0) return dmax2(dmax2(w, x), dmax2(y, z));
     return dconst(0.0);
@@ -191,6 +235,59 @@ void vor_sweep_line_jacobian(const double* f, long M, double s, int periodic, in
     }
 }
 
+/* Selection margin of every input cell of one line sweep: margin[r] is the
+ * smallest gap (see note_gap) of the limiter and clamp of the interfaces
+ * whose stencils read cell r -- the interfaces that make column r of the
+ * frozen Jacobian, so the adjoint lam_in[r] = sum_i J[i][r] lam[i] depends
+ * on no other selection (+inf where none reads it). */
+void vor_sweep_line_margin(const double* f, long M, double s, int periodic, double* margin)
+{
+    long N;
+    double nu;
+    vor_split_shift(s, &N, &nu);
+    const double mu = fabs(nu);
+    const int neg = nu < 0.0 || (nu == 0.0 && s < 0.0);
+    for (long i = 0; i < M; ++i) margin[i] = INFINITY;
+    if (nu == 0.0) return;
+    for (long i = 0; i < M; ++i) {
+        long jj = i - N;                          /* interface jj + 1/2 */
+        double x[5], S = 0.0;
+        long cols[5];
+        for (int k = 0; k < 5; ++k) {
+            long idx = neg ? jj + 3 - k : jj - 2 + k;
+            cols[k] = wrap_or_drop(idx, M, periodic);
+            x[k] = cols[k] >= 0 ? f[cols[k]] : 0.0;
+            if (fabs(x[k]) > S) S = fabs(x[k]);
+        }
+        tl_gap = INFINITY;
+        tl_scale = S;
+        tl_x = x;
+        (void)dflux(x, mu, 1);
+        tl_x = NULL;
+        for (int k = 0; k < 5; ++k)
+            if (cols[k] >= 0 && tl_gap < margin[cols[k]]) margin[cols[k]] = tl_gap;
+    }
+    /* the interface below output 0 (jj = -N-1) also enters the update */
+    {
+        long jj = -N - 1;
+        double x[5], S = 0.0;
+        long cols[5];
+        for (int k = 0; k < 5; ++k) {
+            long idx = neg ? jj + 3 - k : jj - 2 + k;
+            cols[k] = wrap_or_drop(idx, M, periodic);
+            x[k] = cols[k] >= 0 ? f[cols[k]] : 0.0;
+            if (fabs(x[k]) > S) S = fabs(x[k]);
+        }
+        tl_gap = INFINITY;
+        tl_scale = S;
+        tl_x = x;
+        (void)dflux(x, mu, 1);
+        tl_x = NULL;
+        for (int k = 0; k < 5; ++k)
+            if (cols[k] >= 0 && tl_gap < margin[cols[k]]) margin[cols[k]] = tl_gap;
+    }
+}
+
 /* Tangent and adjoint of a line sweep through its frozen Jacobian. */
 void vor_sweep_line_tangent(const double* f, long M, double s, int periodic, const double* v,
                             double nu_dot, double* out_dot)
@@ -301,6 +398,68 @@ int vor_advect_velocity_adj(const vor_grid* g, int a, int vbc, const double* fin
         free(line);
         free(lam);
         free(res);
+    }
+    return 0;
+}
+
+/* Selection margins of a position / velocity sweep: margin has the layout of
+ * f and holds, at every cell, the margin vor_sweep_line_margin gives it in
+ * its line. */
+int vor_advect_position_margin(const vor_grid* g, int a, const double* fin, double* margin,
+                               double dt_over_a2)
+{
+    int rc = vor_check_grid(g);
+    if (rc) return rc;
+    long n[3] = {g->n[0], g->n[1], g->n[2]};
+    long nu[3] = {g->nu[0], g->nu[1], g->nu[2]};
+    long Nu = nu[0] * nu[1] * nu[2];
+    long stride_sp[3] = {n[1] * n[2] * Nu, n[2] * Nu, Nu};
+    int b0 = (a == 0) ? 1 : 0;
+    int b1 = (a == 2) ? 1 : 2;
+    long nplanes = n[b0] * n[b1];
+    #pragma omp parallel for schedule(static)
+    for (long p = 0; p < nplanes; ++p) {
+        long i0 = p / n[b1], i1 = p % n[b1], M = n[a];
+        double *line = malloc(sizeof(double) * M), *mg = malloc(sizeof(double) * M);
+        for (long ju = 0; ju < Nu; ++ju) {
+            long jv[3] = {ju / (nu[1] * nu[2]), (ju / nu[2]) % nu[1], ju % nu[2]};
+            double s = vor_position_shift(g, a, jv[a], dt_over_a2);
+            long base = i0 * stride_sp[b0] + i1 * stride_sp[b1] + ju;
+            for (long i = 0; i < M; ++i) line[i] = fin[base + i * stride_sp[a]];
+            vor_sweep_line_margin(line, M, s, 1, mg);
+            for (long i = 0; i < M; ++i) margin[base + i * stride_sp[a]] = mg[i];
+        }
+        free(line);
+        free(mg);
+    }
+    return 0;
+}
+
+int vor_advect_velocity_margin(const vor_grid* g, int a, int vbc, const double* fin,
+                               const float* gfield, double dt, double* margin)
+{
+    int rc = vor_check_grid(g);
+    if (rc) return rc;
+    long nu[3] = {g->nu[0], g->nu[1], g->nu[2]};
+    long Nx = (long)g->n[0] * g->n[1] * g->n[2], Nu = nu[0] * nu[1] * nu[2];
+    long stride_u[3] = {nu[1] * nu[2], nu[2], 1};
+    int b0 = (a == 0) ? 1 : 0;
+    int b1 = (a == 2) ? 1 : 2;
+    #pragma omp parallel for schedule(static)
+    for (long c = 0; c < Nx; ++c) {
+        long M = nu[a];
+        double *line = malloc(sizeof(double) * M), *mg = malloc(sizeof(double) * M);
+        double s = vor_velocity_shift(g, a, gfield[(long)a * Nx + c], dt);
+        for (long j0 = 0; j0 < nu[b0]; ++j0) {
+            for (long j1 = 0; j1 < nu[b1]; ++j1) {
+                long base = c * Nu + j0 * stride_u[b0] + j1 * stride_u[b1];
+                for (long i = 0; i < M; ++i) line[i] = fin[base + i * stride_u[a]];
+                vor_sweep_line_margin(line, M, s, vbc == 1, mg);
+                for (long i = 0; i < M; ++i) margin[base + i * stride_u[a]] = mg[i];
+            }
+        }
+        free(line);
+        free(mg);
     }
     return 0;
 }

@@ -5,11 +5,13 @@ loss L = sum_x (rho(x) - rho_target(x))^2 where rho_target comes from a run
 with perturbed potential amplitudes B (1 + 0.1 xi) and another density
 contrast; gradients with respect to f0 and B through VlasovRun.  Checked by
 a dot-product test of one step, central finite differences (h = 1e-4) along
-16 seeded directions, and the FP64 oracle's chain at 8^3 x 8^3.
+16 seeded directions, and the FP64 oracle at 8^3 x 8^3, sweep by sweep
+and element by element.
 """
 import numpy as np
 import pytest
 
+import adjoint_check
 import oracle
 from paper_2110_15867_amd import inputs
 
@@ -86,7 +88,21 @@ def test_step_dot_product(adjoint_workload):
 
 
 def test_gradients_finite_differences(adjoint_workload):
-    """Central differences, h = 1e-4, along 16 seeded directions in (f0, B)."""
+    """Central differences, h = 1e-4, along 16 seeded directions in (f0, B).
+
+    Four directions move the field only, four f0 only and eight both.  Along
+    white noise in f0, or along f0 times a smooth function of position, the
+    limiter's selections switch within relative steps of 1e-4 at so many
+    interfaces that central differences do not approach the derivative (on
+    the FP64 oracle at 16^3 x 16^3: 9-14 % off the adjoint at h = 1e-4 for
+    white noise, with this limiter and with a fixed alpha = 4 alike, 1 % at
+    h = 1e-6; 6 % at h = 1e-4 and 2 % at h = 1e-5 for smooth modes); the
+    adjoint along such directions is checked by the dot-product test and
+    element by element against the oracle.  Here the f0 part of a direction
+    is f0 times a seeded factor: every sweep is positively homogeneous (each
+    selection compares linear forms of the stencil), so the run maps
+    (1 + t) f0 to (1 + t) times its result, the loss is a quadratic in t and
+    the central difference exact up to rounding."""
     w, prob, pot, rho_t, f0, B = adjoint_workload
     print("case: finite differences", w.name, flush=True)
     f0g = f0.clone().requires_grad_(True)
@@ -100,7 +116,7 @@ def test_gradients_finite_differences(adjoint_workload):
     with torch.no_grad():
         for k in range(16):
             # directions scaled to the variables: relative steps of h
-            df = f0 * torch.from_numpy(rng.standard_normal(f0.shape).astype(np.float32)).cuda()
+            df = f0 * float(rng.standard_normal())
             dB = B * torch.from_numpy(rng.standard_normal(B.shape)).cuda()
             if k % 4 == 0:
                 df = torch.zeros_like(df)      # field-only directions
@@ -119,12 +135,19 @@ def test_gradients_finite_differences(adjoint_workload):
 
 
 def test_gradient_against_fp64_oracle_chain():
-    """The same chain with the FP64 oracle at 8^3 x 8^3 (4 steps, checkpoints every 2)."""
+    """The same chain at 8^3 x 8^3 (4 steps, checkpoints every 2), element by
+    element: the moments adjoint against the oracle's, then every step's nine
+    transposed sweeps against the oracle's on the GPU's own forward states
+    and incoming adjoint (outputs of lines with a selection within 1e-5 of a
+    tie excluded and counted); the chain of those GPU sweeps must give the
+    autograd gradient bit for bit, and the amplitude gradient must match the
+    oracle's chain component by component."""
     w = inputs.scaled(inputs.workload(5), (8, 8, 8), (8, 8, 8))
     nsteps = 4
     print("case: oracle chain", w.name, flush=True)
     prob, pot = _problem(w, nsteps, 2)
     og = oracle.Grid.make(w.n, w.nu, w.L, w.umax)
+    hg = prob.grid
     rng = np.random.default_rng(7)
     f0_np = (inputs.initial_f(w) * (1 + 0.01 * rng.uniform(-1, 1, og.shape))).astype(np.float32)
     rho_t_np = rng.uniform(0.5, 1.5, tuple(w.n)) * 0.1
@@ -134,24 +157,55 @@ def test_gradient_against_fp64_oracle_chain():
     rho = AG.VlasovRun.apply(f0, B, prob)
     L = ((rho - torch.from_numpy(rho_t_np).cuda()) ** 2).sum()
     L.backward()
-    # oracle chain in FP64 (fields are the same float32 arrays)
-    basis = [b.cpu().numpy().astype(np.float64) for b in prob.basis]
-    fields = [np.tensordot(pot.B, b, axes=(0, 0)).astype(np.float32) for b in basis]
-    states = [f0_np.astype(np.float64)]
+    # the GPU's forward states and the chain of its transposed sweeps
+    fields = [AG.field_at(B.detach(), b) for b in prob.basis]
+    states = [f0.detach()]
     for n in range(nsteps):
-        states.append(oracle.step(og, states[-1], fields[n], fields[n + 1], w.dt))
-    rho_o, _, _ = oracle.moments(og, states[-1])
-    lam = oracle.moments_adj(og, states[-1], 2 * (rho_o - rho_t_np).reshape(-1))
-    lamB = np.zeros_like(pot.B)
+        states.append(AG._step(prob, states[-1], fields[n], fields[n + 1],
+                               torch.empty(V.vlasov_step_workspace_bytes(hg, V.F32),
+                                           dtype=torch.uint8, device="cuda")))
+    rho_g, um_g, _ = V.moments(V.State(hg, V.F32, states[-1]))
+    lam_rho = 2 * (rho_g - torch.from_numpy(rho_t_np).cuda())
+    lam = torch.zeros_like(states[-1])
+    V.vlasov_moments_adj(hg, rho_g, um_g, lam_rho.contiguous(), None, lam)
+    torch.cuda.synchronize()
+    ref = oracle.moments_adj(og, states[-1].double().cpu().numpy(), lam_rho.cpu().numpy().reshape(-1))
+    np.testing.assert_allclose(lam.cpu().numpy(), ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max())
+    excl = total = 0
+    lamB = torch.zeros(len(pot.B), dtype=torch.float64, device="cuda")
+    for n in range(nsteps - 1, -1, -1):
+        lam, lgn, lgnp1, e, t = adjoint_check.check_step_adjoint(
+            hg, og, states[n], fields[n], fields[n + 1], w.dt, lam)
+        excl += e
+        total += t
+        lamB += torch.tensordot(prob.basis[n].double(), lgn.double(), dims=([1, 2, 3, 4], [0, 1, 2, 3]))
+        lamB += torch.tensordot(prob.basis[n + 1].double(), lgnp1.double(),
+                                dims=([1, 2, 3, 4], [0, 1, 2, 3]))
+    print(f"oracle chain: {excl} of {total} compared elements excluded as near-ties")
+    # measured: 1.4 % of the compared elements (this coarse grid, eight
+    # velocity cells per axis, empties its outer velocity cells through the
+    # vacuum boundary within a few steps, and a tie of computed values next to
+    # an empty cell counts as a near-tie)
+    assert excl <= 0.02 * total
+    assert torch.equal(f0.grad, lam)
+    # amplitudes: the FP64 oracle's whole chain (a sum over every cell, where
+    # the few near-tie selections weigh little)
+    basis = [b.cpu().numpy().astype(np.float64) for b in prob.basis]
+    flds = [np.tensordot(pot.B, b, axes=(0, 0)).astype(np.float32) for b in basis]
+    st = [f0_np.astype(np.float64)]
+    for n in range(nsteps):
+        st.append(oracle.step(og, st[-1], flds[n], flds[n + 1], w.dt))
+    rho_o, _, _ = oracle.moments(og, st[-1])
+    lo = oracle.moments_adj(og, st[-1], 2 * (rho_o - rho_t_np).reshape(-1))
+    lamB_o = np.zeros_like(pot.B)
     cells = int(np.prod(w.n))
     for n in range(nsteps - 1, -1, -1):
-        lgn, lgnp1 = np.zeros(3 * cells), np.zeros(3 * cells)
-        lam = oracle.step_adj(og, states[n], fields[n], fields[n + 1], w.dt, lam,
-                              lam_g_n=lgn, lam_g_np1=lgnp1)
-        lamB += basis[n].reshape(len(pot.B), -1) @ lgn + basis[n + 1].reshape(len(pot.B), -1) @ lgnp1
-    gf = f0.grad.double().cpu().numpy()
-    rel_f = np.linalg.norm(gf - lam) / np.linalg.norm(lam)
-    rel_B = np.linalg.norm(B.grad.double().cpu().numpy() - lamB) / np.linalg.norm(lamB)
-    print(f"oracle chain: grad f0 rel L2 {rel_f:.2e}, grad B rel L2 {rel_B:.2e}")
-    assert rel_f <= 2e-3          # FP32 vs FP64 selections differ at a few near-ties
-    assert rel_B <= 1e-3
+        lgn_o, lgnp1_o = np.zeros(3 * cells), np.zeros(3 * cells)
+        lo = oracle.step_adj(og, st[n], flds[n], flds[n + 1], w.dt, lo, lam_g_n=lgn_o,
+                             lam_g_np1=lgnp1_o)
+        lamB_o += basis[n].reshape(len(pot.B), -1) @ lgn_o
+        lamB_o += basis[n + 1].reshape(len(pot.B), -1) @ lgnp1_o
+    gB = B.grad.double().cpu().numpy()
+    assert np.allclose(gB, lamB.cpu().numpy(), rtol=1e-12, atol=0)
+    print("amplitude gradient", gB, "oracle", lamB_o)
+    np.testing.assert_allclose(gB, lamB_o, rtol=0, atol=1e-3 * np.abs(lamB_o).max())
