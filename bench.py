@@ -7,12 +7,13 @@ per FP32 copy), with the seeded initial condition and drifting potential of
 ``paper_2110_15867_amd.inputs``.  Inputs and all fields are resident in HBM
 before the timed region.
 
-Prints ONE JSON line: cell-updates/s per full step, the algorithmic HBM rate,
-a roofline entry for the slowest launch (HIP events on the launch stream: the
-fused kick, bound by vector ALU issue, or a drift sweep, bound by HBM), the
-same workload with FP16 storage (speedup against FP32; skipped with
---no-fp16 or when --prec is not f32) and the FP64 CPU oracle timed on a
-bounded sample on the host cores.
+Prints ONE JSON line: cell-updates/s per full step, the algorithmic HBM rate
+of the step against the 8 TB/s peak, a roofline entry for the slowest launch
+(HIP events on the launch stream; every launch streams f once in and once
+out), each kernel's time per timed step, the same workload with FP16 storage
+(speedup against FP32; skipped with --no-fp16 or when --prec is not f32),
+companion timings (merged half kicks, fused moments, the step adjoint) and
+the FP64 CPU oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
 
@@ -28,20 +29,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
-# Vector ALU issue peak without packed FP32: 256 CUs x 64 lanes x 2.4 GHz, one
-# FP32 operation (an FMA counted once) per lane per clock.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-
-# FP32 operations the fused kick needs per cell and sweep: 14 on the path
-# where the unlimited interface value passes the Suresh-Huynh test (four
-# products for the value, one new difference, the test, the clamp and the
-# update), 30 more where it fails and the full bounds are built -- about one
-# interface in ten on this workload's velocity profile.  Scaled storage keeps
-# FP32 values between the three sweeps and adds only the codec, once per kick:
-# decoding (convert, scale) and encoding (largest |value|, scale, convert),
-# five operations per cell, a third of them per sweep.
-KICK_OPS_PER_CELL_SWEEP = {0: 14.0 + 0.10 * 30.0, 1: 14.0 + 0.10 * 30.0 + 5.0 / 3.0,
-                           2: 14.0 + 0.10 * 30.0 + 5.0 / 3.0}
+# The full step should move its algorithmic bytes at this fraction of the HBM
+# peak or better.
+TARGET_FRAC = 0.70
 
 
 def _log(msg):
@@ -206,6 +196,15 @@ def timed_run(V, torch, inputs, w, grid, prec, K, W, dev, stream):
     return {"total_ms": total_ms, "step_ms": step_ms, "per": per, "t_wall": t_wall}
 
 
+def per_step(per, name, K):
+    """Event times of one kernel, one value per timed step (kicks averaged)."""
+    v = per[name]
+    if len(v) == K:
+        return v
+    m = len(v) // K
+    return [statistics.mean(v[k * m:(k + 1) * m]) for k in range(K)]
+
+
 def companion_run(V, torch, inputs, w, grid, prec, K, dev, stream):
     """Two other forms of the same work, for comparison (not the headline):
     K steps through vlasov_steps, whose half kicks between steps run as one
@@ -282,11 +281,65 @@ def companion_run(V, torch, inputs, w, grid, prec, K, dev, stream):
     }
 
 
+def adjoint_companion(V, torch, inputs, dev, stream, reps=3):
+    """vlasov_step_adj on the differentiation workload (32^3 x 16^3, FP32): the
+    eight forward stages recomputed from f, then the nine transposed sweeps.
+    Algorithmic bytes per cell: 8 forward sweeps x 8 B + 9 adjoint sweeps x
+    12 B (read the stage and the incoming adjoint, write the outgoing one)."""
+    w = inputs.workload(5)
+    grid = V.make_grid(w.n, w.nu, w.L, w.umax)
+    f = inputs.initial_f32_device(w, dev)
+    pot = inputs.potential(w)
+    gn = torch.from_numpy(inputs.accel_field(w, pot, 0.0)).to(dev)
+    gnp1 = torch.from_numpy(inputs.accel_field(w, pot, w.dt)).to(dev)
+    lam = torch.ones_like(f)
+    lam_in = torch.empty_like(f)
+    lgn = torch.zeros_like(gn)
+    lgnp1 = torch.zeros_like(gn)
+    nb = V.vlasov_step_adj_workspace_bytes(grid)
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
+    fwd_out = torch.empty_like(f)
+    fwd_nb = V.vlasov_step_workspace_bytes(grid, V.F32)
+    fwd_work = torch.empty(fwd_nb, dtype=torch.uint8, device=dev)
+
+    def adj():
+        V.vlasov_step_adj(grid, V.VBC_OUTFLOW, f, gn, gnp1, w.dt, 1.0, lam, lam_in, lgn, lgnp1,
+                          work, nb, stream)
+
+    def fwd():
+        V.vlasov_step(grid, V.F32, V.VBC_OUTFLOW, f, None, fwd_out, None, gn, gnp1, w.dt, 1.0,
+                      fwd_work, fwd_nb, None, stream)
+
+    def timed(fn):
+        fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    ms_adj, ms_fwd = timed(adj), timed(fwd)
+    bytes_adj = (8 * 8 + 9 * 12) * w.cells
+    del f, lam, lam_in, work, fwd_out, fwd_work
+    torch.cuda.empty_cache()
+    return {
+        "workload": w.name,
+        "step_adj_ms": ms_adj,
+        "step_ms": ms_fwd,
+        "adj_over_step": ms_adj / ms_fwd,
+        "bytes_per_step_adj": bytes_adj,
+        "hbm_tbps_algorithmic": bytes_adj / (ms_adj * 1e-3) / 1e12,
+        "frac": bytes_adj / (ms_adj * 1e-3) / 1e9 / HBM_PEAK_GBS,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--prec", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--workload", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -338,40 +391,28 @@ def main():
     launch_bytes = bpc * w.cells
     achieved_gbs = launch_bytes / (avg[dominant] * 1e-3) / 1e9
     traffic = measured_traffic(prec, dominant, w.nu[0], w.n[0])
-    if dominant == "kick":
-        # the fused kick is bound by vector ALU issue (three sweeps of
-        # arithmetic per HBM round trip), not by HBM
-        launch_ops = KICK_OPS_PER_CELL_SWEEP[prec] * 3 * w.cells
-        achieved_tops = launch_ops / (avg[dominant] * 1e-3) / 1e12
-        roofline = {
-            "bound": "alu",
-            "kernel": "kick",
-            "ops_per_launch": launch_ops,
-            "achieved": achieved_tops,
-            "peak": VALU_PEAK_TOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tops / VALU_PEAK_TOPS,
-            "traffic": traffic,
-            "hbm_bytes_per_launch": launch_bytes,
-            "hbm_achieved_gbs": achieved_gbs,
-            "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
-        }
-    else:
-        roofline = {
-            "bound": "hbm",
-            "kernel": f"sweep {dominant}",
-            "bytes_per_launch": launch_bytes,
-            "achieved": achieved_gbs,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved_gbs / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "frac_of_copy_probe": achieved_gbs / copy_gbs,
-        }
+    # Every launch streams f once in and once out: the roofline is HBM.  The
+    # fused kick does three sweeps of arithmetic per round trip, so its
+    # fraction of the HBM peak also shows how far its ALU work is from hiding
+    # behind the memory traffic.
+    roofline = {
+        "bound": "hbm",
+        "kernel": "kick (ux, uy, uz fused)" if dominant == "kick" else f"sweep {dominant}",
+        "bytes_per_launch": launch_bytes,
+        "achieved": achieved_gbs,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved_gbs / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "frac_of_copy_probe": achieved_gbs / copy_gbs,
+    }
     _log("bench: per-kernel ms " + json.dumps({k: round(v, 3) for k, v in avg.items()}))
+    for nm in per:
+        _log(f"bench: {nm} ms per step " + " ".join(f"{x:.2f}" for x in per_step(per, nm, K)))
 
     value = w.cells * K / (total_ms * 1e-3)
     step_bytes = 5 * launch_bytes              # two fused kicks and three drifts
+    step_frac = step_bytes / (total_ms / K * 1e-3) / 1e9 / HBM_PEAK_GBS
     res = {
         "metric": "6D phase-space cell-updates/sec per full step",
         "value": value,
@@ -391,10 +432,17 @@ def main():
         "config": {"workload": w.name, "nx": list(w.n), "nu": list(w.nu), "L": list(w.L),
                    "dt": w.dt, "sweeps_per_step": 9, "launches_per_step": 5,
                    "storage": args.prec},
+        # the bytes the five launches of a step must move (one read and one
+        # write of f each), over the step time
         "hbm_tbps_algorithmic": step_bytes / (total_ms / K * 1e-3) / 1e12,
-        # the nine sweeps of Eq. (5) counted separately, as if unfused
-        "hbm_tbps_nine_sweep_equivalent": 9 * launch_bytes / (total_ms / K * 1e-3) / 1e12,
+        "step_hbm_frac": step_frac,
+        "step_hbm_target_frac": TARGET_FRAC,
+        "step_hbm_gap_to_target": TARGET_FRAC - step_frac,
         "kernel_ms": {k: round(v, 4) for k, v in avg.items()},
+        # per timed step: each kernel's event time (the kick entry is the mean
+        # of the step's two kicks), to tell a trend over the run from noise
+        "kernel_ms_per_step": {k: [round(x, 3) for x in per_step(per, k, K)]
+                               for k in per},
         "copy_probe_gbs": copy_gbs,
         "roofline": roofline,
     }
@@ -417,6 +465,8 @@ def main():
     if not args.no_companions:
         _log("bench: companion timings (merged half kicks, fused moments)")
         res["companions"] = companion_run(V, torch, inputs, w, grid, prec, K, dev, stream)
+        _log("bench: companion timing (step adjoint)")
+        res["companions"]["step_adjoint"] = adjoint_companion(V, torch, inputs, dev, stream)
     if not args.no_cpu_baseline:
         _log("bench: timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline()
