@@ -167,7 +167,7 @@ __device__ FluxLin flux_lin(const Stencil& s, const LineShift& sh, const WeightS
     FluxLin out;
     // the value: flux_mag's own operations
     float pre_v = sh.mu * (s.c + y);
-    if (!early) pre_v = mp_flux(s, sh, y);
+    if (!early) pre_v = mp_flux<true>(s, sh, y);
     out.phi = med3(pre_v, 0.0f, s.c);
     VL r;
     if (!sh.comp) {

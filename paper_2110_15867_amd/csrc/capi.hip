@@ -149,6 +149,25 @@ int make_pos_args(const vlasov_grid* g, const Dims& d, int axis, double dt_over_
     }
     if (axis == 2) a.pair = pair_mode(a);
     a.skew = axis != 2;
+    // a wave covers 64 V consecutive inner elements; they share the shift
+    // when the velocity index that sets it changes only every pst elements
+    a.us = a.pst % (64L * a.V) == 0 ? 1 : 0;
+    // whether a wave-aligned block of 64 V inner elements can hold lanes of
+    // both directions (shift signs); the inner index repeats with period Nu
+    a.mix = 0;
+    const long span = 64L * a.V;
+    if (a.V != 4 || (a.I / a.V) % 64 != 0) {
+        a.mix = 1;
+    } else {
+        for (long k0 = 0; k0 < a.Nu && !a.mix; k0 += span) {
+            const long j_lo = (k0 / a.pst) % a.nshift;
+            const long j_hi = ((k0 + span - 1) / a.pst) % a.nshift;
+            const bool n_lo = a.shift[j_lo] < 0.0, n_hi = a.shift[j_hi] < 0.0;
+            // within a block the index runs monotonically from j_lo to j_hi
+            // (span divides Nu), and u_j, hence the shift, is monotone in j
+            if (n_lo != n_hi || j_hi < j_lo) a.mix = 1;
+        }
+    }
     return VLASOV_OK;
 }
 

@@ -21,6 +21,8 @@ struct PosArgs {
     int G;           // lanes per uz-line (scaled storage)
     int pair;        // z sweep with the halves of each uz-line paired per lane (0: no)
     int skew;        // waves start their walks at different rows (1) or all at row 0
+    int us;          // every wave's lanes share one shift and rows hold whole waves (1)
+    int mix;         // some wave holds lanes that move in both directions (1)
     double shift[kMaxShiftTable];   // s_j = u_j dt a^-2 / dx per velocity index
 };
 

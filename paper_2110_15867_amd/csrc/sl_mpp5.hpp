@@ -264,14 +264,32 @@ __device__ __forceinline__ float mp_bounded(float fhat, const Stencil& s, float 
 // Flux (before the positivity clamp) of an interface whose unlimited value
 // fails the Suresh-Huynh test.  comp lines bound the complement ghat on the
 // mirrored stencil (e, d, c, b, a) and return f_j - mu' ghat_lim (see
-// LineShift); the flag is uniform over a line, so a wave whose lanes share
-// the shift takes one branch.
+// LineShift).  UNI: branch on the line's flag -- one branch when the lanes of
+// the wave agree, and a wave whose lanes all take the same side skips the
+// other; otherwise each lane picks its stencil orientation and constants by
+// select and one set of bounds is evaluated (for waves whose lanes mix both
+// kinds of line throughout, as in the y sweep).  The same operations per lane
+// either way.
+template <bool UNI>
 __device__ __forceinline__ float mp_flux(const Stencil& s, const LineShift& sh, float y)
 {
-    if (!sh.comp) return sh.mu * mp_bounded(s.c + y, s, sh.alpha);
-    const Stencil m{s.e, s.d, s.c, s.b, s.a, -s.dp1, -s.d0, -s.dm1, -s.dm2};
-    const float ghat = fmaf(-sh.q, y, s.c);
-    return fmaf(-sh.muc, mp_bounded(ghat, m, sh.alpha_c), s.c);
+    if (UNI) {
+        if (!sh.comp) return sh.mu * mp_bounded(s.c + y, s, sh.alpha);
+        const Stencil m{s.e, s.d, s.c, s.b, s.a, -s.dp1, -s.d0, -s.dm1, -s.dm2};
+        const float ghat = fmaf(-sh.q, y, s.c);
+        return fmaf(-sh.muc, mp_bounded(ghat, m, sh.alpha_c), s.c);
+    }
+    // (q and alpha_c are recomputed here, as split_shift computes them, so
+    // that they hold no registers across the walk)
+    const bool c = sh.comp;
+    const float q = sh.mu / sh.muc;
+    const float ac = mp_alpha(sh.muc);
+    const Stencil t{c ? s.e : s.a, c ? s.d : s.b, s.c, c ? s.b : s.d, c ? s.a : s.e,
+                    c ? -s.dp1 : s.dm2, c ? -s.d0 : s.dm1, c ? -s.dm1 : s.d0,
+                    c ? -s.dm2 : s.dp1};
+    const float fh = c ? fmaf(-q, y, s.c) : s.c + y;
+    const float lim = mp_bounded(fh, t, c ? ac : sh.alpha);
+    return c ? fmaf(-sh.muc, lim, s.c) : sh.mu * lim;
 }
 
 // Flux magnitude through the interface j+1/2 in its upwind frame: the SL
@@ -284,6 +302,7 @@ __device__ __forceinline__ float mp_flux(const Stencil& s, const LineShift& sh, 
 // The unlimited value is formed as f_j + (fhat - f_j) from the carried
 // differences (four products instead of five, and fhat - f_j is what the
 // test needs).
+template <bool UNI = true>
 __device__ __forceinline__ float flux_mag(const Stencil& s, const LineShift& sh)
 {
     float y = sh.v0 * s.dm2;                            // fhat - f_j
@@ -292,9 +311,29 @@ __device__ __forceinline__ float flux_mag(const Stencil& s, const LineShift& sh)
     y = fmaf(sh.v3, s.dp1, y);
     const float m = med3(s.d0, sh.alpha * s.dm1, 0.0f); // f_MP - f_j
     float pre = sh.mu * (s.c + y);
-    if (__builtin_expect(med3(y, 0.0f, m) != y, 0)) pre = mp_flux(s, sh, y);
+    if (__builtin_expect(med3(y, 0.0f, m) != y, 0)) pre = mp_flux<UNI>(s, sh, y);
     // positivity: what leaves the upwind cell lies between 0 and its content
     return med3(pre, 0.0f, s.c);
+}
+
+// The constants of a line whose shift is the same in every lane of the wave,
+// moved to scalar registers.
+__device__ __forceinline__ LineShift uniform_shift(const LineShift& sh)
+{
+    LineShift u = sh;
+    u.N = uniform_sgpr(sh.N);
+    u.neg = uniform_sgpr(sh.neg ? 1 : 0) != 0;
+    u.comp = uniform_sgpr(sh.comp ? 1 : 0) != 0;
+    u.mu = uniform_f32(sh.mu);
+    u.alpha = uniform_f32(sh.alpha);
+    u.q = uniform_f32(sh.q);
+    u.alpha_c = uniform_f32(sh.alpha_c);
+    u.muc = uniform_f32(sh.muc);
+    u.v0 = uniform_f32(sh.v0);
+    u.v1 = uniform_f32(sh.v1);
+    u.v2 = uniform_f32(sh.v2);
+    u.v3 = uniform_f32(sh.v3);
+    return u;
 }
 
 // ---------------------------------------------------------------------------
@@ -346,7 +385,7 @@ struct RowPipe {
 // MT > 0 fixes the line length at compile time (full unroll, and for
 // periodic lines the first five rows are kept instead of re-read).
 // ---------------------------------------------------------------------------
-template <int V, int MT, class Reader, class Writer>
+template <int V, int MT, bool UNI, class Reader, class Writer>
 __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int Mrt,
                                              const LineShift& sh, const bool periodic,
                                              float* ofl)
@@ -391,8 +430,8 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
         dm1[v] = x0[v] - xm1[v];
         d0[v] = xp1[v] - x0[v];
         dp1[v] = xp2[v] - xp1[v];
-        phi_old[v] = flux_mag(Stencil{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v], dm1[v], d0[v],
-                                      dp1[v]}, sh);
+        phi_old[v] = flux_mag<UNI>(Stencil{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v], dm1[v],
+                                           d0[v], dp1[v]}, sh);
         xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v];
         dm2[v] = dm1[v]; dm1[v] = d0[v]; d0[v] = dp1[v];
     }
@@ -417,8 +456,8 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             dp1[v] = xp2[v] - xp1[v];
-            const float phi = flux_mag(Stencil{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v],
-                                               dm1[v], d0[v], dp1[v]}, sh);
+            const float phi = flux_mag<UNI>(Stencil{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v],
+                                                    dm1[v], d0[v], dp1[v]}, sh);
             res[v] = x0[v] - (phi - phi_old[v]);
             phi_old[v] = phi;
             xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v];
@@ -544,7 +583,7 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
         q2[v] = xp1[v] - x0[v];
         q3[v] = xp2[v] - xp1[v];
         q4[v] = xp3[v] - xp2[v];
-        phi_old[v] = flux_mag(mixed_stencil(neg, xm2[v], xm1[v], x0[v], xp1[v], xp2[v], xp3[v],
+        phi_old[v] = flux_mag<true>(mixed_stencil(neg, xm2[v], xm1[v], x0[v], xp1[v], xp2[v], xp3[v],
                                             q0[v], q1[v], q2[v], q3[v], q4[v]), sh);
         xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v]; xp2[v] = xp3[v];
         q0[v] = q1[v]; q1[v] = q2[v]; q2[v] = q3[v]; q3[v] = q4[v];
@@ -563,7 +602,7 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             q4[v] = xp3[v] - xp2[v];
-            const float phi = flux_mag(mixed_stencil(neg, xm2[v], xm1[v], x0[v], xp1[v], xp2[v],
+            const float phi = flux_mag<true>(mixed_stencil(neg, xm2[v], xm1[v], x0[v], xp1[v], xp2[v],
                                                      xp3[v], q0[v], q1[v], q2[v], q3[v], q4[v]),
                                        sh);
             res[v] = fmaf(-sgn, phi - phi_old[v], x0[v]);
@@ -631,8 +670,8 @@ __device__ __forceinline__ void walk_pair(Reader& rd, Writer& wr, const LineShif
         da[q] = a[q + 1] - a[q];
         mb[q] = b[q] - b[q + 1];
     }
-    phia = flux_mag(Stencil{a[0], a[1], a[2], a[3], a[4], da[0], da[1], da[2], da[3]}, sa);
-    gb = flux_mag(Stencil{b[4], b[3], b[2], b[1], b[0], mb[3], mb[2], mb[1], mb[0]}, sb);
+    phia = flux_mag<true>(Stencil{a[0], a[1], a[2], a[3], a[4], da[0], da[1], da[2], da[3]}, sa);
+    gb = flux_mag<true>(Stencil{b[4], b[3], b[2], b[1], b[0], mb[3], mb[2], mb[1], mb[0]}, sb);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         a[q] = a[q + 1];
@@ -657,8 +696,8 @@ __device__ __forceinline__ void walk_pair(Reader& rd, Writer& wr, const LineShif
         b[4] = x[1];
         da[3] = a[4] - a[3];
         mb[3] = b[3] - b[4];
-        const float pa_new = flux_mag(Stencil{a[0], a[1], a[2], a[3], a[4], da[0], da[1], da[2], da[3]}, sa);
-        const float gb_new = flux_mag(Stencil{b[4], b[3], b[2], b[1], b[0], mb[3], mb[2], mb[1], mb[0]}, sb);
+        const float pa_new = flux_mag<true>(Stencil{a[0], a[1], a[2], a[3], a[4], da[0], da[1], da[2], da[3]}, sa);
+        const float gb_new = flux_mag<true>(Stencil{b[4], b[3], b[2], b[1], b[0], mb[3], mb[2], mb[1], mb[0]}, sb);
         const float ra_out = a[2] - (pa_new - phia);
         const float rb_out = b[1] + (gb_new - gb);
         phia = pa_new;

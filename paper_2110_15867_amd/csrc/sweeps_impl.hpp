@@ -41,7 +41,7 @@ namespace vlasov {
 // ---------------------------------------------------------------------------
 // Position sweeps
 // ---------------------------------------------------------------------------
-template <int P, int V, int MT, int GC>
+template <int P, int V, int MT, int GC, bool US, bool MIX>
 __global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __restrict__ fin,
                                                   const float* __restrict__ sin,
                                                   typename Codec<P>::T* __restrict__ fout,
@@ -61,6 +61,29 @@ __global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __
     const long sI = a.I / a.nuz;                 // uz-lines per row
     const long sb = o * (long)M * sI + k / a.nuz;
 
+    if constexpr (US) {
+        // The host guarantees that every lane of a wave has the same shift
+        // (x sweeps: a wave's elements share u_x) and that rows hold whole
+        // waves: one direction, one integer shift, wave-uniform row
+        // addresses and line constants in scalar registers.
+        const LineShift shu = uniform_shift(sh);
+        const long t0 = t - (threadIdx.x & 63);
+        const long o0 = t0 / IV;
+        const long k0 = (t0 - o0 * IV) * V;
+        const long ub = uniform_long(o0 * (long)M * a.I + k0);
+        const long usb = uniform_long(o0 * (long)M * sI + k0 / a.nuz);
+        const unsigned loff = (unsigned)((k - k0) * (long)sizeof(typename Codec<P>::T));
+        const unsigned soff = (unsigned)((k / a.nuz - k0 / a.nuz) * (long)sizeof(float));
+        const unsigned nb = (unsigned)uniform_sgpr(
+            (int)row_span_bytes((a.I - k0) * (long)sizeof(typename Codec<P>::T)));
+        const unsigned snb = (unsigned)uniform_sgpr((int)row_span_bytes((sI - k0 / a.nuz) * (long)sizeof(float)));
+        const int r0 = a.skew ? uniform_sgpr((int)(((t0 >> 6) * 17) % M)) : 0;
+        const int dir = shu.neg ? -1 : 1;
+        URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, dir, r0, 0};
+        URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, dir, r0, a.G};
+        walk_uniform<V, MT, true>(rd, wr, M, shu, true, nullptr);
+        return;
+    }
     const unsigned long long neg_lanes = __ballot(sh.neg);
     const unsigned long long act = __ballot(1);
     const bool one_dir = neg_lanes == 0 || neg_lanes == act;
@@ -91,22 +114,22 @@ __global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __
         shu.N = uniform_sgpr(sh.N);
         // x and y: each wave starts its walk at its own row (see URowWriter)
         const int r0 = a.skew ? uniform_sgpr((int)(((t0 >> 6) * 17) % M)) : 0;
-        if (one_dir) {
+        if (!MIX || one_dir) {
             const int dir = uniform_sgpr(sh.neg ? -1 : 1);
             URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, dir, r0, 0};
             URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, dir, r0, a.G};
-            walk_uniform<V, MT>(rd, wr, M, shu, true, nullptr);
-        } else {
+            walk_uniform<V, MT, false>(rd, wr, M, shu, true, nullptr);
+        } else if constexpr (MIX) {
             URowReader<P, V> rd{fin + ub, sin + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, 1, r0, 0};
             URowWriter<P, V, GC> wr{fout + ub, sout + (Codec<P>::scaled ? usb : 0), loff, soff, nb, snb, a.I, sI, M, 1, r0, a.G};
             walk_mixed<V, MT>(rd, wr, M, uniform_sgpr(Ns), shu);
         }
-    } else if (one_dir) {
+    } else if (!MIX || one_dir) {
         const int dir = sh.neg ? -1 : 1;
         GlobalReader<P, V> rd{fin + lbase, sin + (Codec<P>::scaled ? sb : 0), a.I, sI, M, dir, true, 0};
         GlobalWriter<P, V, GC> wr{fout + lbase, sout + (Codec<P>::scaled ? sb : 0), a.I, sI, M, dir, a.G};
-        walk_uniform<V, MT>(rd, wr, M, sh, true, nullptr);
-    } else {
+        walk_uniform<V, MT, false>(rd, wr, M, sh, true, nullptr);
+    } else if constexpr (MIX) {
         GlobalReader<P, V> rd{fin + lbase, sin + (Codec<P>::scaled ? sb : 0), a.I, sI, M, 1, true, 0};
         GlobalWriter<P, V, GC> wr{fout + lbase, sout + (Codec<P>::scaled ? sb : 0), a.I, sI, M, 1, a.G};
         walk_mixed<V, MT>(rd, wr, M, Ns, sh);
@@ -189,7 +212,7 @@ __global__ void __launch_bounds__(256) k_vel_strided(const typename Codec<P>::T*
         GlobalReader<P, V> rd{fin + lbase, sin + (Codec<P>::scaled ? sb : 0), a.I, sI, M, dir, a.periodic, 0};
         GlobalWriter<P, V> wr{fout + lbase, sout + (Codec<P>::scaled ? sb : 0), a.I, sI, M, dir, a.G};
         float ofl = 0.0f;
-        walk_uniform<V, MT>(rd, wr, M, sh, a.periodic, &ofl);
+        walk_uniform<V, MT, true>(rd, wr, M, sh, a.periodic, &ofl);
         mine += (double)ofl;
     }
     if (a.outflow != nullptr && !a.periodic) {
@@ -237,7 +260,7 @@ __global__ void __launch_bounds__(NT) k_vel_uz(const typename Codec<P>::T* __res
         float ofl = 0.0f;
         if (threadIdx.x < nl) {
             LdsReader rd{tile + threadIdx.x * LS, 1, MT, dir, a.periodic, 0};
-            walk_uniform<1, MT>(rd, wr, MT, sh, a.periodic, &ofl);
+            walk_uniform<1, MT, true>(rd, wr, MT, sh, a.periodic, &ofl);
             mine += (double)ofl;
         }
         __syncthreads();
@@ -303,15 +326,15 @@ __global__ void __launch_bounds__(256) k_vel_uz_generic(const typename Codec<P>:
             };
             ScaledReader srd{rd, sc};
             MaxWriter mw{0.0f};
-            walk_uniform<1, 0>(srd, mw, M, sh, a.periodic, &ofl);
+            walk_uniform<1, 0, true>(srd, mw, M, sh, a.periodic, &ofl);
             inv = inv_scale(mw.m);
             sout[line] = mw.m;
             ScaledReader srd2{rd, sc};
             ContigWriter<P> cw{fout + line * M, M, dir, inv};
-            walk_uniform<1, 0>(srd2, cw, M, sh, a.periodic, &ofl);
+            walk_uniform<1, 0, true>(srd2, cw, M, sh, a.periodic, &ofl);
         } else {
             ContigWriter<P> cw{fout + line * M, M, dir, 1.0f};
-            walk_uniform<1, 0>(rd, cw, M, sh, a.periodic, &ofl);
+            walk_uniform<1, 0, true>(rd, cw, M, sh, a.periodic, &ofl);
         }
         mine += (double)ofl;
     }
@@ -353,9 +376,19 @@ inline hipError_t launch_position_v(const void* fin, const float* sin, void* fou
     // group size of the scale reduction
     constexpr int G32 = Codec<P>::scaled ? 32 / V : 0;
     const bool g32 = G32 > 0 && a.G == G32;
+    // waves whose lanes all share the shift (x sweeps) get the variant with
+    // the line constants in scalar registers; where no wave holds lanes of
+    // both directions (y sweeps of the usual blocks) the mixed walk is left
+    // out, which frees registers
+    const bool us = a.us != 0 && V == 4;
+    const bool mix = a.mix != 0 || V != 4;
 #define VL_POS(MTV) \
-    if (g32) hipLaunchKernelGGL((k_position<P, V, MTV, G32>), dim3(blocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a); \
-    else hipLaunchKernelGGL((k_position<P, V, MTV, 0>), dim3(blocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a)
+    if (us && g32) hipLaunchKernelGGL((k_position<P, V, MTV, G32, true, false>), dim3(blocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a); \
+    else if (us) hipLaunchKernelGGL((k_position<P, V, MTV, 0, true, false>), dim3(blocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a); \
+    else if (!mix && g32) hipLaunchKernelGGL((k_position<P, V, MTV, G32, false, false>), dim3(blocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a); \
+    else if (!mix) hipLaunchKernelGGL((k_position<P, V, MTV, 0, false, false>), dim3(blocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a); \
+    else if (g32) hipLaunchKernelGGL((k_position<P, V, MTV, G32, false, true>), dim3(blocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a); \
+    else hipLaunchKernelGGL((k_position<P, V, MTV, 0, false, true>), dim3(blocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a)
     switch (a.M) {
         case 16: VL_POS(16); break;
         case 32: VL_POS(32); break;
