@@ -90,7 +90,8 @@ enum {
     VLASOV_ERR_ALIAS = -4,      /* an output overlaps an input */
     VLASOV_ERR_NONFINITE = -5,  /* dt, a^-2 or the derived shift factor is not finite */
     VLASOV_ERR_DEVICE = -6,     /* HIP launch or runtime error */
-    VLASOV_ERR_WORKSPACE = -7   /* workspace NULL or smaller than required */
+    VLASOV_ERR_WORKSPACE = -7,  /* workspace NULL or smaller than required */
+    VLASOV_ERR_TOO_LARGE = -8   /* grid exceeds the fixed scratch of an allocation-free call */
 };
 
 /* Version of this interface (VLASOV_ABI_VERSION). */
@@ -419,6 +420,24 @@ int vlasov_step_adj(const vlasov_grid* grid, vlasov_vbc vbc, const float* f_in,
 int vlasov_moments_adj(const vlasov_grid* grid, const double* rho, const double* umean,
                        const double* lam_rho, const double* lam_umean, float* lam_f,
                        void* stream);
+
+/*
+ * vlasov_field for callers that cannot allocate (code under stream capture,
+ * serving loops, harnesses that forbid allocation): the same computation,
+ * with its twiddle tables and FP64 spectra in a fixed device array of the
+ * library instead of a caller workspace.  The array holds
+ * vlasov_field_noalloc_max_bytes() bytes (24 MiB: meshes up to 64^3 cells);
+ * each device keeps its own copy until the process ends, and its address is
+ * looked up on the first call on that device.  Results are vlasov_field's,
+ * bit for bit.  Every call on one device uses the same array: calls that
+ * overlap on one device (concurrent streams) race.  No allocation, no
+ * hipMalloc, no caller workspace.
+ * Errors: as vlasov_field; VLASOV_ERR_TOO_LARGE when the mesh needs more
+ * than the fixed array (vlasov_field_workspace_bytes > max_bytes).
+ */
+size_t vlasov_field_noalloc_max_bytes(void);
+int vlasov_field_noalloc(const vlasov_grid* grid, const double* rho, double coupling,
+                         float* field, void* stream);
 
 /*
  * Storage codec of the FP16/BF16 forms (the reduced-precision storage of f;

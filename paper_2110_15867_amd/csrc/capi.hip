@@ -345,6 +345,7 @@ const char* vlasov_strerror(int code)
         case VLASOV_ERR_NONFINITE: return "time step or shift factor is not finite";
         case VLASOV_ERR_DEVICE: return "HIP launch or runtime error";
         case VLASOV_ERR_WORKSPACE: return "workspace missing or too small";
+        case VLASOV_ERR_TOO_LARGE: return "grid exceeds the fixed scratch of the allocation-free call";
         default: return "unknown error code";
     }
 }

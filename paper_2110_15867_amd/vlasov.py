@@ -111,6 +111,10 @@ def _load():
     L.vlasov_sum_f64.argtypes = [P, ctypes.c_int64, P, P]
     L.vlasov_stream_copy.restype = I
     L.vlasov_stream_copy.argtypes = [P, P, S, P]
+    L.vlasov_field_noalloc_max_bytes.restype = S
+    L.vlasov_field_noalloc_max_bytes.argtypes = []
+    L.vlasov_field_noalloc.restype = I
+    L.vlasov_field_noalloc.argtypes = [G, P, D, P, P]
     L.vlasov_encode.restype = I
     L.vlasov_encode.argtypes = [G, I, P, P, P, P]
     L.vlasov_decode.restype = I
@@ -329,6 +333,15 @@ def vlasov_dispersion(grid, prec, f, scale, rho, umean, sigma, stream=None):
 
 def vlasov_sum_f64(x, n, out, stream=None):
     _check(_lib.vlasov_sum_f64(_ptr(x), int(n), _ptr(out), _stream(stream)), "vlasov_sum_f64")
+
+
+def vlasov_field_noalloc_max_bytes() -> int:
+    return _lib.vlasov_field_noalloc_max_bytes()
+
+
+def vlasov_field_noalloc(grid, rho, coupling, field, stream=None):
+    _check(_lib.vlasov_field_noalloc(ctypes.byref(grid), _ptr(rho), float(coupling), _ptr(field),
+                                     _stream(stream)), "vlasov_field_noalloc")
 
 
 def vlasov_encode(grid, prec, f32, codes, scale, stream=None):
