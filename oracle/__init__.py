@@ -18,7 +18,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle_vlasov.so")
+# VLASOV_ORACLE_LIB selects another build of the same sources (the sanitizer
+# build of the CPU test run)
+_LIB_PATH = os.environ.get("VLASOV_ORACLE_LIB", os.path.join(_HERE, "liboracle_vlasov.so"))
 _lib = None
 
 c_double_p = ctypes.POINTER(ctypes.c_double)

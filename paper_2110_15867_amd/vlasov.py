@@ -15,10 +15,13 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvlasov.so")
+# VLASOV_LIB selects another build of the same sources (the sanitizer build of
+# the host code, for the CPU test run)
+LIB_PATH = os.environ.get("VLASOV_LIB", os.path.join(_HERE, "libvlasov.so"))
 
 F32, F16, BF16 = 0, 1, 2
 VBC_OUTFLOW, VBC_PERIODIC = 0, 1
@@ -455,6 +458,40 @@ def decode(state: State, stream=None) -> torch.Tensor:
     out = torch.empty(state.f.shape, dtype=torch.float32, device=state.f.device)
     vlasov_decode(state.grid, state.prec, state.f, state.scale, out, stream)
     return out
+
+
+def save(path, state: State, step: int = 0, t: float = 0.0, outflow=None):
+    """Write a state to an .npz file (no pickled objects): the grid, the
+    storage precision, f bit for bit (FP16/BF16 codes as their 16-bit
+    patterns), the scales, the step index, the time and optionally the
+    per-cell outflow tally."""
+    g = state.grid
+    f = state.f.detach()
+    bits = f.view(torch.int16) if state.prec != F32 else f
+    arrays = {
+        "n": np.array(list(g.n), np.int64), "nu": np.array(list(g.nu), np.int64),
+        "L": np.array(list(g.L), np.float64), "umax": np.array(list(g.umax), np.float64),
+        "prec": np.array(int(state.prec), np.int64), "step": np.array(int(step), np.int64),
+        "t": np.array(float(t), np.float64), "f": bits.cpu().numpy(),
+    }
+    if state.scale is not None:
+        arrays["scale"] = state.scale.detach().cpu().numpy()
+    if outflow is not None:
+        arrays["outflow"] = outflow.detach().cpu().numpy()
+    np.savez(path, **arrays)
+
+
+def load(path, device="cuda"):
+    """Read a state written by save: (State, step, t, outflow or None)."""
+    with np.load(path, allow_pickle=False) as z:
+        grid = make_grid(tuple(z["n"]), tuple(z["nu"]), tuple(z["L"]), tuple(z["umax"]))
+        prec = int(z["prec"])
+        f = torch.from_numpy(z["f"]).to(device)
+        if prec != F32:
+            f = f.view(TORCH_DTYPE[prec])
+        scale = torch.from_numpy(z["scale"]).to(device) if "scale" in z else None
+        outflow = torch.from_numpy(z["outflow"]).to(device) if "outflow" in z else None
+        return State(grid, prec, f.contiguous(), scale), int(z["step"]), float(z["t"]), outflow
 
 
 def advect(axis: str, state: State, dt, g=None, vbc=VBC_OUTFLOW, outflow=None, stream=None):

@@ -11,7 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "vlasov.h")
-LIB = os.path.join(ROOT, "paper_2110_15867_amd", "libvlasov.so")
+LIB = os.environ.get("VLASOV_LIB", os.path.join(ROOT, "paper_2110_15867_amd", "libvlasov.so"))
 
 
 def _declared():
