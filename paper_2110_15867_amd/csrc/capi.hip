@@ -141,6 +141,7 @@ int make_pos_args(const vlasov_grid* g, const Dims& d, int axis, double dt_over_
     a.pst = axis == 0 ? d.nu[1] * d.nu[2] : (axis == 1 ? d.nu[2] : 1);
     a.nshift = (int)d.nu[axis];
     a.nuz = d.nu[2];
+    a.nux = d.nu[0];
     a.V = axis == 2 ? 1 : vector_width(d.nu[2]);
     a.G = (int)(d.nu[2] / a.V);
     for (long j = 0; j < d.nu[axis]; ++j) {
@@ -152,6 +153,21 @@ int make_pos_args(const vlasov_grid* g, const Dims& d, int axis, double dt_over_
     // a wave covers 64 V consecutive inner elements; they share the shift
     // when the velocity index that sets it changes only every pst elements
     a.us = a.pst % (64L * a.V) == 0 ? 1 : 0;
+    // y sweep: the shift follows u_y, which changes every nu_z elements.  A
+    // wave can still hold one u_y value if its lanes take R = 64 V / nu_z
+    // whole uz-lines from R consecutive u_x rows (k_position's gathered
+    // mapping): nu_z / V lanes per uz-line making up the wave, R dividing
+    // nu_x, nu_y a multiple of 4 (4 waves of a work-group share a unit),
+    // rows of whole work-groups and units filling groups of eight.
+    a.ug = 0;
+    // (taken for FP32 storage only -- k_position decides: an FP16/BF16
+    // uz-line is 64 bytes, and a gathered wave would read half cache lines)
+    if (axis == 1 && !a.us && a.V == 4 && (64L * a.V) % a.nuz == 0 &&
+        (a.I / a.V) % 256 == 0 && d.nu[1] % 4 == 0) {
+        const long R = 64L * a.V / a.nuz;
+        const long units = a.O * (a.I / a.Nu) * (d.nu[0] / (R > 0 ? R : 1));
+        if (R > 1 && d.nu[0] % R == 0 && (a.nuz / a.V) * R == 64 && units % 8 == 0) a.ug = (int)R;
+    }
     // whether a wave-aligned block of 64 V inner elements can hold lanes of
     // both directions (shift signs); the inner index repeats with period Nu
     a.mix = 0;

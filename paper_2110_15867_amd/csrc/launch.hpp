@@ -17,11 +17,15 @@ struct PosArgs {
     long pst;        // stride of the velocity index that sets the shift
     int nshift;      // velocity cells along the matching velocity axis
     long nuz;        // length of a uz-line (scale granularity)
+    long nux;        // velocity cells along u_x
     int V;           // adjacent inner elements per thread
     int G;           // lanes per uz-line (scaled storage)
     int pair;        // z sweep with the halves of each uz-line paired per lane (0: no)
     int skew;        // waves start their walks at different rows (1) or all at row 0
     int us;          // every wave's lanes share one shift and rows hold whole waves (1)
+    int ug;          // y sweep: waves can be gathered across u_x so that they share u_y
+                     // (the number of uz-lines per wave, each from its own u_x row), or
+                     // 0; used with FP32 storage
     int mix;         // some wave holds lanes that move in both directions (1)
     double shift[kMaxShiftTable];   // s_j = u_j dt a^-2 / dx per velocity index
 };

@@ -245,7 +245,19 @@ struct Stencil {
     float dm2, dm1, d0, dp1;
 };
 
-// The bounded value median(fhat, fmin, fmax) of the Suresh-Huynh constraint.
+// The bounded value median(fhat, fmin, fmax) of the Suresh-Huynh constraint,
+// given the curvature minmods d^M4 at j-1/2 (Mm) and j+1/2 (Mp).
+__device__ __forceinline__ float mp_bounded_m(float fhat, const Stencil& s, float alpha, float Mm,
+                                              float Mp)
+{
+    const float fUL = fmaf(alpha, s.dm1, s.c);
+    const float fMD = 0.5f * ((s.c + s.d) - Mp);
+    const float fLC = fmaf(4.0f / 3.0f, Mm, fmaf(0.5f, s.dm1, s.c));
+    const float lo = fmaxf(fminf(fminf(s.c, s.d), fMD), fminf(fminf(s.c, fUL), fLC));
+    const float hi = fminf(fmaxf(fmaxf(s.c, s.d), fMD), fmaxf(fmaxf(s.c, fUL), fLC));
+    return med3(fhat, lo, hi);
+}
+
 __device__ __forceinline__ float mp_bounded(float fhat, const Stencil& s, float alpha)
 {
     const float Dm = s.dm1 - s.dm2;                 // curvature at j-1
@@ -253,12 +265,7 @@ __device__ __forceinline__ float mp_bounded(float fhat, const Stencil& s, float 
     const float Dp = s.dp1 - s.d0;                  // curvature at j+1
     const float Mp = curv_minmod(D0, Dp);           // d^M4 at j+1/2
     const float Mm = curv_minmod(Dm, D0);           // d^M4 at j-1/2
-    const float fUL = fmaf(alpha, s.dm1, s.c);
-    const float fMD = 0.5f * ((s.c + s.d) - Mp);
-    const float fLC = fmaf(4.0f / 3.0f, Mm, fmaf(0.5f, s.dm1, s.c));
-    const float lo = fmaxf(fminf(fminf(s.c, s.d), fMD), fminf(fminf(s.c, fUL), fLC));
-    const float hi = fminf(fmaxf(fmaxf(s.c, s.d), fMD), fmaxf(fmaxf(s.c, fUL), fLC));
-    return med3(fhat, lo, hi);
+    return mp_bounded_m(fhat, s, alpha, Mm, Mp);
 }
 
 // Flux (before the positivity clamp) of an interface whose unlimited value
@@ -313,6 +320,35 @@ __device__ __forceinline__ float flux_mag(const Stencil& s, const LineShift& sh)
     float pre = sh.mu * (s.c + y);
     if (__builtin_expect(med3(y, 0.0f, m) != y, 0)) pre = mp_flux<UNI>(s, sh, y);
     // positivity: what leaves the upwind cell lies between 0 and its content
+    return med3(pre, 0.0f, s.c);
+}
+
+// flux_mag with the curvature minmods d^M4 at j-1/2 (Mm) and j+1/2 (Mp)
+// supplied by a walker that evaluates every interface of a line in order:
+// d^M4 at j+1/2 is d^M4 at j-1/2 of the next interface (the minmod is
+// symmetric in its two curvatures, so the values are the very bits
+// mp_bounded would compute), so one minmod per interface is evaluated
+// outside the test and the bounds left behind it cost eleven operations.
+// The mirrored stencil of a comp line swaps the two.  Same result as
+// flux_mag, bit for bit.
+__device__ __forceinline__ float flux_mag_mm(const Stencil& s, const LineShift& sh, float Mm,
+                                             float Mp)
+{
+    float y = sh.v0 * s.dm2;                            // fhat - f_j
+    y = fmaf(sh.v1, s.dm1, y);
+    y = fmaf(sh.v2, s.d0, y);
+    y = fmaf(sh.v3, s.dp1, y);
+    const float m = med3(s.d0, sh.alpha * s.dm1, 0.0f); // f_MP - f_j
+    float pre = sh.mu * (s.c + y);
+    if (__builtin_expect(med3(y, 0.0f, m) != y, 0)) {
+        if (!sh.comp) {
+            pre = sh.mu * mp_bounded_m(s.c + y, s, sh.alpha, Mm, Mp);
+        } else {
+            const Stencil r{s.e, s.d, s.c, s.b, s.a, -s.dp1, -s.d0, -s.dm1, -s.dm2};
+            const float ghat = fmaf(-sh.q, y, s.c);
+            pre = fmaf(-sh.muc, mp_bounded_m(ghat, r, sh.alpha_c, Mp, Mm), s.c);
+        }
+    }
     return med3(pre, 0.0f, s.c);
 }
 
@@ -394,6 +430,8 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
     const int N = sh.N;
     float xm2[V], xm1[V], x0[V], xp1[V], xp2[V], phi_old[V];
     float dm2[V], dm1[V], d0[V], dp1[V];    // x_{j-1}-x_{j-2}, ..., x_{j+2}-x_{j+1}
+    // UNI: curvature at j and d^M4 at j-1/2, carried (flux_mag_mm)
+    float cj[V], kj[V];
     float head[5][V];
     float acc = 0.0f;
     int r = -N - 3;                       // frame row of the next value
@@ -430,8 +468,16 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
         dm1[v] = x0[v] - xm1[v];
         d0[v] = xp1[v] - x0[v];
         dp1[v] = xp2[v] - xp1[v];
-        phi_old[v] = flux_mag<UNI>(Stencil{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v], dm1[v],
-                                           d0[v], dp1[v]}, sh);
+        const Stencil st{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v], dm1[v], d0[v], dp1[v]};
+        if constexpr (UNI) {
+            const float c0 = d0[v] - dm1[v], cp = dp1[v] - d0[v];
+            const float Mp = curv_minmod(c0, cp);
+            phi_old[v] = flux_mag_mm(st, sh, curv_minmod(dm1[v] - dm2[v], c0), Mp);
+            cj[v] = cp;
+            kj[v] = Mp;
+        } else {
+            phi_old[v] = flux_mag<UNI>(st, sh);
+        }
         xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v];
         dm2[v] = dm1[v]; dm1[v] = d0[v]; d0[v] = dp1[v];
     }
@@ -456,8 +502,17 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             dp1[v] = xp2[v] - xp1[v];
-            const float phi = flux_mag<UNI>(Stencil{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v],
-                                                    dm1[v], d0[v], dp1[v]}, sh);
+            const Stencil st{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v], dm1[v], d0[v], dp1[v]};
+            float phi;
+            if constexpr (UNI) {
+                const float cp = dp1[v] - d0[v];
+                const float Mp = curv_minmod(cj[v], cp);
+                phi = flux_mag_mm(st, sh, kj[v], Mp);
+                cj[v] = cp;
+                kj[v] = Mp;
+            } else {
+                phi = flux_mag<UNI>(st, sh);
+            }
             res[v] = x0[v] - (phi - phi_old[v]);
             phi_old[v] = phi;
             xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v];
@@ -505,23 +560,33 @@ __device__ __forceinline__ float line_update_regs(const float (&x)[M], const Lin
                                                   Emit&& emit)
 {
     auto X = [&](int k) { return line_cell<M, PER>(x, k); };
+    // curvature minmods carried from interface to interface (flux_mag_mm)
+    const float e0 = X(-2) - X(-3), e1 = X(-1) - X(-2), e2 = X(0) - X(-1), e3 = X(1) - X(0);
+    const float Dm1 = e2 - e1;                        // curvature at cell -1
+    float D0 = e3 - e2;                               // curvature at cell 0
+    float Mm = curv_minmod(e1 - e0, Dm1);             // d^M4 at -3/2
     // Phi_{-1/2}: the interface below cell 0 (for PER the one at the top)
     float phi_prev = 0.0f;
-    if (!PER) {
-        phi_prev = flux_mag(Stencil{X(-3), X(-2), X(-1), X(0), X(1), X(-2) - X(-3),
-                                    X(-1) - X(-2), X(0) - X(-1), X(1) - X(0)}, sh);
+    {
+        const float Mp = curv_minmod(Dm1, D0);        // d^M4 at -1/2
+        if (!PER) phi_prev = flux_mag_mm(Stencil{X(-3), X(-2), X(-1), X(0), X(1), e0, e1, e2, e3},
+                                         sh, Mm, Mp);
+        Mm = Mp;
     }
-    float dm2 = X(-1) - X(-2), dm1 = X(0) - X(-1), d0 = X(1) - X(0);
+    float dm2 = e1, dm1 = e2, d0 = e3;
     float phi_first = 0.0f;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
         const float dp1 = X(j + 2) - X(j + 1);
-        const float phi = flux_mag(Stencil{X(j - 2), X(j - 1), X(j), X(j + 1), X(j + 2), dm2, dm1,
-                                           d0, dp1}, sh);
+        const float Dp = dp1 - d0;                    // curvature at j+1
+        const float Mp = curv_minmod(D0, Dp);         // d^M4 at j+1/2
+        const float phi = flux_mag_mm(Stencil{X(j - 2), X(j - 1), X(j), X(j + 1), X(j + 2), dm2,
+                                              dm1, d0, dp1}, sh, Mm, Mp);
         if (PER && j == 0) phi_first = phi;
         if (!PER || j > 0) emit(j, X(j) - (phi - phi_prev));
         phi_prev = phi;
         dm2 = dm1; dm1 = d0; d0 = dp1;
+        D0 = Dp; Mm = Mp;
     }
     if (PER) emit(0, X(0) - (phi_first - phi_prev));   // Phi_{-1/2} = Phi_{M-1/2}
     return phi_prev;
@@ -562,6 +627,11 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
     const int Ns = Nsgn;                  // out_i = x_{i-Ns} - (Phi_{i-Ns+1/2} - Phi_{i-Ns-1/2})
     float xm2[V], xm1[V], x0[V], xp1[V], xp2[V], xp3[V], phi_old[V];
     float q0[V], q1[V], q2[V], q3[V], q4[V];   // x_{j-1}-x_{j-2}, ..., x_{j+3}-x_{j+2}
+    // carried for flux_mag_mm: curvatures at j+1, j+2 and K_i = d^M4 at
+    // i-1/2 (the minmod of the curvatures at i-1 and i) for i = j .. j+2.
+    // The stencil of a lane moving up has d^M4 = K_j below and K_{j+1}
+    // above; a mirrored lane's (upwind cell j+1) has K_{j+2} and K_{j+1}.
+    float c1[V], c2[V], k0[V], k1[V], k2[V];
     float head[6][V];
     rd.seek(-Ns - 3);
     rd.next(xm2); rd.next(xm1); rd.next(x0); rd.next(xp1); rd.next(xp2); rd.next(xp3);
@@ -583,8 +653,15 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
         q2[v] = xp1[v] - x0[v];
         q3[v] = xp2[v] - xp1[v];
         q4[v] = xp3[v] - xp2[v];
-        phi_old[v] = flux_mag<true>(mixed_stencil(neg, xm2[v], xm1[v], x0[v], xp1[v], xp2[v], xp3[v],
-                                            q0[v], q1[v], q2[v], q3[v], q4[v]), sh);
+        const float cm1 = q1[v] - q0[v], c0 = q2[v] - q1[v];
+        c1[v] = q3[v] - q2[v];
+        c2[v] = q4[v] - q3[v];
+        k0[v] = curv_minmod(cm1, c0);
+        k1[v] = curv_minmod(c0, c1[v]);
+        k2[v] = curv_minmod(c1[v], c2[v]);
+        phi_old[v] = flux_mag_mm(mixed_stencil(neg, xm2[v], xm1[v], x0[v], xp1[v], xp2[v], xp3[v],
+                                               q0[v], q1[v], q2[v], q3[v], q4[v]),
+                                 sh, neg ? k2[v] : k0[v], k1[v]);
         xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v]; xp2[v] = xp3[v];
         q0[v] = q1[v]; q1[v] = q2[v]; q2[v] = q3[v]; q3[v] = q4[v];
     }
@@ -602,9 +679,13 @@ __device__ __forceinline__ void walk_mixed(Reader& rd, Writer& wr, const int Mrt
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             q4[v] = xp3[v] - xp2[v];
-            const float phi = flux_mag<true>(mixed_stencil(neg, xm2[v], xm1[v], x0[v], xp1[v], xp2[v],
-                                                     xp3[v], q0[v], q1[v], q2[v], q3[v], q4[v]),
-                                       sh);
+            const float c3 = q4[v] - q3[v];
+            const float k3 = curv_minmod(c2[v], c3);
+            k0[v] = k1[v]; k1[v] = k2[v]; k2[v] = k3;
+            c1[v] = c2[v]; c2[v] = c3;
+            const float phi = flux_mag_mm(mixed_stencil(neg, xm2[v], xm1[v], x0[v], xp1[v], xp2[v],
+                                                        xp3[v], q0[v], q1[v], q2[v], q3[v], q4[v]),
+                                          sh, neg ? k2[v] : k0[v], k1[v]);
             res[v] = fmaf(-sgn, phi - phi_old[v], x0[v]);
             phi_old[v] = phi;
             xm2[v] = xm1[v]; xm1[v] = x0[v]; x0[v] = xp1[v]; xp1[v] = xp2[v]; xp2[v] = xp3[v];
@@ -670,8 +751,18 @@ __device__ __forceinline__ void walk_pair(Reader& rd, Writer& wr, const LineShif
         da[q] = a[q + 1] - a[q];
         mb[q] = b[q] - b[q + 1];
     }
-    phia = flux_mag<true>(Stencil{a[0], a[1], a[2], a[3], a[4], da[0], da[1], da[2], da[3]}, sa);
-    gb = flux_mag<true>(Stencil{b[4], b[3], b[2], b[1], b[0], mb[3], mb[2], mb[1], mb[0]}, sb);
+    // carried for flux_mag_mm.  A: the newest curvature (da[3] - da[2]) and
+    // d^M4 at the upper face (the next interface's lower one).  B (mirrored
+    // stencil, differences mb[3..0]): the curvature mb[2] - mb[3] and d^M4
+    // at the mirrored lower face (the next interface's upper one).
+    float ca = da[3] - da[2];
+    float ka = curv_minmod(da[2] - da[1], ca);
+    float cb = mb[2] - mb[3];
+    float kb = curv_minmod(cb, mb[1] - mb[2]);
+    phia = flux_mag_mm(Stencil{a[0], a[1], a[2], a[3], a[4], da[0], da[1], da[2], da[3]}, sa,
+                       curv_minmod(da[1] - da[0], da[2] - da[1]), ka);
+    gb = flux_mag_mm(Stencil{b[4], b[3], b[2], b[1], b[0], mb[3], mb[2], mb[1], mb[0]}, sb, kb,
+                     curv_minmod(mb[1] - mb[2], mb[0] - mb[1]));
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         a[q] = a[q + 1];
@@ -696,8 +787,18 @@ __device__ __forceinline__ void walk_pair(Reader& rd, Writer& wr, const LineShif
         b[4] = x[1];
         da[3] = a[4] - a[3];
         mb[3] = b[3] - b[4];
-        const float pa_new = flux_mag<true>(Stencil{a[0], a[1], a[2], a[3], a[4], da[0], da[1], da[2], da[3]}, sa);
-        const float gb_new = flux_mag<true>(Stencil{b[4], b[3], b[2], b[1], b[0], mb[3], mb[2], mb[1], mb[0]}, sb);
+        const float ca_new = da[3] - da[2];
+        const float ka_new = curv_minmod(ca, ca_new);
+        const float pa_new = flux_mag_mm(Stencil{a[0], a[1], a[2], a[3], a[4], da[0], da[1], da[2], da[3]},
+                                         sa, ka, ka_new);
+        ca = ca_new;
+        ka = ka_new;
+        const float cb_new = mb[2] - mb[3];
+        const float kb_new = curv_minmod(cb_new, cb);
+        const float gb_new = flux_mag_mm(Stencil{b[4], b[3], b[2], b[1], b[0], mb[3], mb[2], mb[1], mb[0]},
+                                         sb, kb_new, kb);
+        cb = cb_new;
+        kb = kb_new;
         const float ra_out = a[2] - (pa_new - phia);
         const float rb_out = b[1] + (gb_new - gb);
         phia = pa_new;

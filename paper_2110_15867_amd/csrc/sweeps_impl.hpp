@@ -51,8 +51,42 @@ __global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long total = a.O * IV;
     if (t >= total) return;
-    const long o = t / IV;
-    const long k = (t - o * IV) * V;
+    long o = t / IV;
+    long k = (t - o * IV) * V;
+    long k0w = 0;                                  // gathered mapping: lane 0's element
+    const bool gathered = !Codec<P>::scaled && a.ug > 0;
+    if constexpr (US) {
+        if (gathered) {
+            // Gathered mapping (y sweep).  A wave holds R = a.ug uz-lines,
+            // one from each of R consecutive u_x rows, all at the same u_y:
+            // lane l takes elements (l % G) V .. +V-1 of uz-line l / G
+            // (G = nu_z / V lanes per line).  A unit (o, spatial cell of
+            // the row, group of R u_x rows) has nu_y such waves, 4 to a
+            // work-group, Q = nu_y / 4 work-groups.  Work-groups go to the
+            // eight XCDs in turn, so the Q work-groups of a unit are taken
+            // eight apart: they run on one XCD, whose L2 then holds the
+            // 128-byte lines (scales, FP16 codes of neighbouring u_y) that
+            // they share.  The host checks that the units fill whole
+            // groups of eight.
+            const long Q = a.nshift / 4;
+            const long b = blockIdx.x;
+            const long sup = b / (8 * Q);
+            const long rem = b - sup * 8 * Q;
+            const long unit = sup * 8 + rem % 8;
+            const long jy = (rem / 8) * 4 + (threadIdx.x >> 6);
+            const int lane = (int)(threadIdx.x & 63);
+            const long ngx = a.nux / a.ug;              // u_x groups per block
+            const long upr = (a.I / a.Nu) * ngx;        // units per row
+            o = unit / upr;
+            const long ur = unit - o * upr;
+            const long blk = ur / ngx;
+            const long jxg = ur - blk * ngx;
+            const int G = (int)(a.nuz / V);
+            const int rr = lane / G;
+            k0w = blk * a.Nu + (jxg * a.ug * a.nshift + jy) * a.nuz;
+            k = k0w + ((long)rr * a.nshift) * a.nuz + (long)(lane - rr * G) * V;
+        }
+    }
     const int M = MT > 0 ? MT : a.M;
     const int jl = (int)(((k % a.Nu) / a.pst) % a.nshift);
     const LineShift sh = split_shift(a.shift[jl], M, true);
@@ -63,13 +97,14 @@ __global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __
 
     if constexpr (US) {
         // The host guarantees that every lane of a wave has the same shift
-        // (x sweeps: a wave's elements share u_x) and that rows hold whole
-        // waves: one direction, one integer shift, wave-uniform row
-        // addresses and line constants in scalar registers.
+        // (x sweeps: a wave's elements share u_x; gathered y sweeps: u_y)
+        // and that rows hold whole waves: one direction, one integer shift,
+        // wave-uniform row addresses and line constants in scalar registers.
         const LineShift shu = uniform_shift(sh);
         const long t0 = t - (threadIdx.x & 63);
-        const long o0 = t0 / IV;
-        const long k0 = (t0 - o0 * IV) * V;
+        // the wave's row and first element (lane 0's)
+        const long o0 = gathered ? o : t0 / IV;
+        const long k0 = gathered ? uniform_long(k0w) : (t0 - o0 * IV) * V;
         const long ub = uniform_long(o0 * (long)M * a.I + k0);
         const long usb = uniform_long(o0 * (long)M * sI + k0 / a.nuz);
         const unsigned loff = (unsigned)((k - k0) * (long)sizeof(typename Codec<P>::T));
@@ -380,7 +415,7 @@ inline hipError_t launch_position_v(const void* fin, const float* sin, void* fou
     // the line constants in scalar registers; where no wave holds lanes of
     // both directions (y sweeps of the usual blocks) the mixed walk is left
     // out, which frees registers
-    const bool us = a.us != 0 && V == 4;
+    const bool us = (a.us != 0 || (a.ug > 0 && !Codec<P>::scaled)) && V == 4;
     const bool mix = a.mix != 0 || V != 4;
 #define VL_POS(MTV) \
     if (us && g32) hipLaunchKernelGGL((k_position<P, V, MTV, G32, true, false>), dim3(blocks), dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a); \
