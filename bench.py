@@ -12,7 +12,8 @@ of the step against the 8 TB/s peak, a roofline entry for the slowest launch
 (HIP events on the launch stream; every launch streams f once in and once
 out), each kernel's time per timed step, the same workload with FP16 storage
 (speedup against FP32; skipped with --no-fp16 or when --prec is not f32),
-companion timings (merged half kicks, fused moments, the step adjoint) and
+companion timings (merged half kicks, fused moments, the step adjoint, 64^3
+velocity blocks) and
 the FP64 CPU oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
@@ -281,6 +282,47 @@ def companion_run(V, torch, inputs, w, grid, prec, K, dev, stream):
     }
 
 
+def velocity64_companion(V, torch, inputs, dev, stream, reps=3):
+    """vlasov_step (FP32) with 64^3 velocity blocks: the throughput workload's
+    recipe on 32^3 x 64^3 cells (as many cells as the headline grid).  A
+    64^3 block does not fit a work-group's LDS, so each kick runs its three
+    velocity sweeps as separate launches: nine sweeps per step, each reading
+    and writing 8 B per cell."""
+    w = inputs.scaled(inputs.workload(3), (32, 32, 32), (64, 64, 64))
+    grid = V.make_grid(w.n, w.nu, w.L, w.umax)
+    state = V.State(grid, V.F32, inputs.initial_f32_device(w, dev))
+    pot = inputs.potential(w)
+    gn = torch.from_numpy(inputs.accel_field(w, pot, 0.0)).to(dev)
+    gnp1 = torch.from_numpy(inputs.accel_field(w, pot, w.dt)).to(dev)
+    out = V.empty_state(grid, V.F32, dev)
+    nb = V.vlasov_step_workspace_bytes(grid, V.F32)
+    work = torch.empty(nb, dtype=torch.uint8, device=dev)
+
+    def step():
+        V.vlasov_step(grid, V.F32, V.VBC_OUTFLOW, state.f, None, out.f, None, gn, gnp1, w.dt,
+                      1.0, work, nb, None, stream)
+
+    step()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        step()
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    bytes_step = 9 * 8 * w.cells
+    del state, out, work
+    torch.cuda.empty_cache()
+    return {
+        "workload": w.name,
+        "value": w.cells / (ms * 1e-3),
+        "unit": "cell-updates/s",
+        "ms_per_step": ms,
+        "launches_per_step": 9,
+        "hbm_tbps_algorithmic": bytes_step / (ms * 1e-3) / 1e12,
+    }
+
+
 def adjoint_companion(V, torch, inputs, dev, stream, reps=3):
     """vlasov_step_adj on the differentiation workload (32^3 x 16^3, FP32): the
     eight forward stages recomputed from f, then the nine transposed sweeps.
@@ -467,6 +509,8 @@ def main():
         res["companions"] = companion_run(V, torch, inputs, w, grid, prec, K, dev, stream)
         _log("bench: companion timing (step adjoint)")
         res["companions"]["step_adjoint"] = adjoint_companion(V, torch, inputs, dev, stream)
+        _log("bench: companion timing (64^3 velocity blocks)")
+        res["companions"]["velocity_64"] = velocity64_companion(V, torch, inputs, dev, stream)
     if not args.no_cpu_baseline:
         _log("bench: timing the CPU oracle")
         res["cpu_baseline"] = cpu_baseline()
