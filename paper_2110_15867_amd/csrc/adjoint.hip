@@ -20,8 +20,11 @@
 // mirrored, where mu = -nu).  The adjoint gathers: each input cell is written
 // once, from a sliding window of the five interfaces that read it.
 //
-// One thread per line with direct strided loads: these kernels run once per
-// gradient evaluation and favour simplicity over bandwidth.
+// One thread per line.  Lines along x, y, z, ux and uy are read with direct
+// strided loads (neighbouring lanes take neighbouring elements of a row, so
+// every access is coalesced); the contiguous uz-lines go through LDS tiles of
+// whole lines, loaded and stored with 16-byte accesses, as in the forward uz
+// sweep.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -257,9 +260,10 @@ __device__ void line_tangent(Reader32& rx, Reader32& rv, float* out, long stride
 
 // Adjoint of one line: x = forward input, lam = output adjoint (frame rows
 // read through rl, which starts N rows later).  Writes lam_in and returns
-// lam_mu.
-__device__ float line_adjoint(Reader32& rx, Reader32& rl, float* lam_in, long stride, int M,
-                              int dir, const LineShift& sh, bool periodic)
+// lam_mu.  R: a row reader of global memory (Reader32) or of an LDS tile.
+template <class R>
+__device__ float line_adjoint(R& rx, R& rl, float* lam_in, long stride, int M, int dir,
+                              const LineShift& sh, bool periodic)
 {
     const WeightSlopes ds = sl5_weight_slopes(sh.mu);
     const int N = sh.N;
@@ -275,7 +279,7 @@ __device__ float line_adjoint(Reader32& rx, Reader32& rl, float* lam_in, long st
     float psi[5], W[5][5];
     float lam_mu = 0.0f;
     // identity term source: lam_{r+N} for r = j-2 -> read separately
-    Reader32 rid = rl;
+    R rid = rl;
     rid.seek(N);                                     // lam_{0+N}
     for (int j = -2; j <= M + 1; ++j) {
         if (j > -2) {
@@ -395,6 +399,62 @@ __global__ void __launch_bounds__(256) k_velocity_adj(const float* __restrict__ 
     }
 }
 
+// Adjoint of the uz sweep: the lines are contiguous (M values), so a
+// work-group stages NT whole lines of f and of lam through LDS with 16-byte
+// loads, each thread walks one line out of LDS into a third tile, and the
+// results leave with 16-byte stores.  lam_mu is summed per cell as in
+// k_velocity_adj (per thread over its lines, then over the work-group).
+template <int MT, int NT>
+__global__ void __launch_bounds__(NT) k_velocity_adj_uz(const float* __restrict__ f,
+                                                        const float* __restrict__ lam,
+                                                        float* __restrict__ lam_in,
+                                                        float* __restrict__ lam_g, VelArgs a)
+{
+    constexpr int LS = MT + 1;                  // padded line stride in LDS
+    __shared__ float tf[NT * LS], tl[NT * LS], to[NT * LS];
+    __shared__ double red[NT / 64];
+    const long cell = blockIdx.x;
+    const double s = (double)a.g[cell] * a.factor;
+    const LineShift sh = split_shift(s, MT, a.periodic);
+    const int dir = sh.neg ? -1 : 1;
+    const long lpc = a.nsub;                    // lines per cell = nux * nuy
+    const long cbase = cell * lpc;
+    double mine = 0.0;
+    for (long l0 = 0; l0 < lpc; l0 += NT) {
+        const int nl = (int)((lpc - l0) < NT ? (lpc - l0) : NT);
+        const long off0 = (cbase + l0) * MT;
+        for (int e = threadIdx.x * 4; e < nl * MT; e += NT * 4) {
+            const int ln = e / MT;
+            const int off = e - ln * MT;
+            const float4 x = *reinterpret_cast<const float4*>(f + off0 + e);
+            const float4 y = *reinterpret_cast<const float4*>(lam + off0 + e);
+            float* df = tf + ln * LS + off;
+            float* dl = tl + ln * LS + off;
+            df[0] = x.x; df[1] = x.y; df[2] = x.z; df[3] = x.w;
+            dl[0] = y.x; dl[1] = y.y; dl[2] = y.z; dl[3] = y.w;
+        }
+        __syncthreads();
+        if (threadIdx.x < nl) {
+            LdsReader rx{tf + threadIdx.x * LS, 1, MT, dir, a.periodic, 0};
+            LdsReader rl{tl + threadIdx.x * LS, 1, MT, dir, a.periodic, 0};
+            mine += (double)line_adjoint(rx, rl, to + threadIdx.x * LS, 1, MT, dir, sh,
+                                         a.periodic);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x * 4; e < nl * MT; e += NT * 4) {
+            const int ln = e / MT;
+            const int off = e - ln * MT;
+            const float* src = to + ln * LS + off;
+            *reinterpret_cast<float4*>(lam_in + off0 + e) = make_float4(src[0], src[1], src[2], src[3]);
+        }
+        __syncthreads();
+    }
+    if (lam_g != nullptr) {
+        const double tot = block_sum(mine, red);
+        if (threadIdx.x == 0) lam_g[cell] += (float)((sh.neg ? -tot : tot) * a.factor);
+    }
+}
+
 hipError_t launch_position_tan(const float* f, const float* v, float* out, const PosArgs& a,
                                hipStream_t st)
 {
@@ -434,6 +494,25 @@ hipError_t launch_velocity_adj(const float* f, const float* lam, float* lam_in, 
                                const VelArgs& a, hipStream_t st)
 {
     if (a.cells == 0) return hipSuccess;
+    // uz (contiguous lines of 16, 32 or 64 values, 16-byte aligned cells):
+    // LDS tiles of 4096 values per array
+    const bool al = ((uintptr_t)f | (uintptr_t)lam | (uintptr_t)lam_in) % 16 == 0;
+    if (a.I == 1 && al) {
+        const dim3 grid((unsigned)a.cells);
+        switch (a.M) {
+            case 16:
+                hipLaunchKernelGGL((k_velocity_adj_uz<16, 256>), grid, dim3(256), 0, st, f, lam, lam_in, lam_g, a);
+                return hipGetLastError();
+            case 32:
+                hipLaunchKernelGGL((k_velocity_adj_uz<32, 128>), grid, dim3(128), 0, st, f, lam, lam_in, lam_g, a);
+                return hipGetLastError();
+            case 64:
+                hipLaunchKernelGGL((k_velocity_adj_uz<64, 64>), grid, dim3(64), 0, st, f, lam, lam_in, lam_g, a);
+                return hipGetLastError();
+            default:
+                break;
+        }
+    }
     hipLaunchKernelGGL(k_velocity_adj, dim3((unsigned)a.cells), dim3(vel_block(a)), 0, st, f,
                        lam, lam_in, lam_g, a);
     return hipGetLastError();
