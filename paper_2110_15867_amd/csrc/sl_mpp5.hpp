@@ -331,6 +331,10 @@ __device__ __forceinline__ float flux_mag(const Stencil& s, const LineShift& sh)
 // outside the test and the bounds left behind it cost eleven operations.
 // The mirrored stencil of a comp line swaps the two.  Same result as
 // flux_mag, bit for bit.
+// UNI: branch on the line's comp flag (as mp_flux<true>); otherwise each lane
+// picks its orientation by select (as mp_flux<false>) -- mp_bounded_m reads
+// only c, d, dm1 and the two minmods of the stencil, so four selects orient it.
+template <bool UNI = true>
 __device__ __forceinline__ float flux_mag_mm(const Stencil& s, const LineShift& sh, float Mm,
                                              float Mp)
 {
@@ -341,12 +345,24 @@ __device__ __forceinline__ float flux_mag_mm(const Stencil& s, const LineShift& 
     const float m = med3(s.d0, sh.alpha * s.dm1, 0.0f); // f_MP - f_j
     float pre = sh.mu * (s.c + y);
     if (__builtin_expect(med3(y, 0.0f, m) != y, 0)) {
-        if (!sh.comp) {
-            pre = sh.mu * mp_bounded_m(s.c + y, s, sh.alpha, Mm, Mp);
+        if (UNI) {
+            if (!sh.comp) {
+                pre = sh.mu * mp_bounded_m(s.c + y, s, sh.alpha, Mm, Mp);
+            } else {
+                const Stencil r{s.e, s.d, s.c, s.b, s.a, -s.dp1, -s.d0, -s.dm1, -s.dm2};
+                const float ghat = fmaf(-sh.q, y, s.c);
+                pre = fmaf(-sh.muc, mp_bounded_m(ghat, r, sh.alpha_c, Mp, Mm), s.c);
+            }
         } else {
-            const Stencil r{s.e, s.d, s.c, s.b, s.a, -s.dp1, -s.d0, -s.dm1, -s.dm2};
-            const float ghat = fmaf(-sh.q, y, s.c);
-            pre = fmaf(-sh.muc, mp_bounded_m(ghat, r, sh.alpha_c, Mp, Mm), s.c);
+            const bool c = sh.comp;
+            const float q = sh.mu / sh.muc;
+            const float ac = mp_alpha(sh.muc);
+            Stencil t = s;
+            t.d = c ? s.b : s.d;
+            t.dm1 = c ? -s.d0 : s.dm1;
+            const float fh = c ? fmaf(-q, y, s.c) : s.c + y;
+            const float lim = mp_bounded_m(fh, t, c ? ac : sh.alpha, c ? Mp : Mm, c ? Mm : Mp);
+            pre = c ? fmaf(-sh.muc, lim, s.c) : sh.mu * lim;
         }
     }
     return med3(pre, 0.0f, s.c);
@@ -430,7 +446,12 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
     const int N = sh.N;
     float xm2[V], xm1[V], x0[V], xp1[V], xp2[V], phi_old[V];
     float dm2[V], dm1[V], d0[V], dp1[V];    // x_{j-1}-x_{j-2}, ..., x_{j+2}-x_{j+1}
-    // UNI: curvature at j and d^M4 at j-1/2, carried (flux_mag_mm)
+    // curvature at j and d^M4 at j-1/2, carried (flux_mag_mm).  Carrying
+    // adds a minmod per interface outside the early-out test and saves two
+    // behind it: it pays where the test fails often.  Not for waves of single
+    // lines with per-lane shifts (one-direction waves of the z sweep), where
+    // it was measured to cost time.
+    constexpr bool CARRY = UNI || V > 1;
     float cj[V], kj[V];
     float head[5][V];
     float acc = 0.0f;
@@ -469,10 +490,10 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
         d0[v] = xp1[v] - x0[v];
         dp1[v] = xp2[v] - xp1[v];
         const Stencil st{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v], dm1[v], d0[v], dp1[v]};
-        if constexpr (UNI) {
+        if constexpr (CARRY) {
             const float c0 = d0[v] - dm1[v], cp = dp1[v] - d0[v];
             const float Mp = curv_minmod(c0, cp);
-            phi_old[v] = flux_mag_mm(st, sh, curv_minmod(dm1[v] - dm2[v], c0), Mp);
+            phi_old[v] = flux_mag_mm<UNI>(st, sh, curv_minmod(dm1[v] - dm2[v], c0), Mp);
             cj[v] = cp;
             kj[v] = Mp;
         } else {
@@ -504,10 +525,10 @@ __device__ __forceinline__ void walk_uniform(Reader& rd, Writer& wr, const int M
             dp1[v] = xp2[v] - xp1[v];
             const Stencil st{xm2[v], xm1[v], x0[v], xp1[v], xp2[v], dm2[v], dm1[v], d0[v], dp1[v]};
             float phi;
-            if constexpr (UNI) {
+            if constexpr (CARRY) {
                 const float cp = dp1[v] - d0[v];
                 const float Mp = curv_minmod(cj[v], cp);
-                phi = flux_mag_mm(st, sh, kj[v], Mp);
+                phi = flux_mag_mm<UNI>(st, sh, kj[v], Mp);
                 cj[v] = cp;
                 kj[v] = Mp;
             } else {
