@@ -82,6 +82,30 @@ def measured_traffic(prec: int, kernel: str, nu: int, nx: int):
     return hits[0] if len(hits) == 1 else None
 
 
+# MI355X vector ALU issue rate without packed FP32 instructions (the kernels
+# are built without them): 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
+# (each wave64 VALU instruction occupies a SIMD for four clocks).
+VALU_PEAK_TLANE_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def measured_valu(prec: int, kernel: str, nu: int, nx: int):
+    """VALU lane-operations per dispatch (SQ_INSTS_VALU x 64) from the committed
+    rocprofv3 counter summary, if it was taken on the current sources of the
+    profiled kernels (else None)."""
+    path = os.path.join(ROOT, "profiles", "valu_counts.json")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path)).get({0: "f32", 1: "f16", 2: "bf16"}[prec])
+    if not data or data.get("source_sha256") != kernel_source_hash():
+        return None
+    if kernel == "kick":
+        prefix = f"k_kick<{prec}, {nu}, "
+    else:
+        prefix = f"k_position<{prec}, {1 if kernel == 'z' else 4}, {nx}, "
+    hits = [v for k, v in data["lane_ops_per_dispatch"].items() if k.startswith(prefix)]
+    return hits[0] if len(hits) == 1 else None
+
+
 def cpu_baseline(seconds: float = 12.0):
     """FP64 oracle Strang step on the 16^3 x 16^3 workload (same recipe), host cores."""
     import numpy as np
@@ -424,6 +448,19 @@ def main():
     copy_gbs = 5 * 2 * probe_bytes / (pe[0].elapsed_time(pe[1]) * 1e-3) / 1e9
     del a_buf, b_buf
     _log(f"bench: copy probe {copy_gbs:.0f} GB/s (read + write)")
+    # the vector-ALU ceiling: independent FP32 chains over 2^20 threads
+    vbuf = torch.empty(1 << 20, dtype=torch.float32, device=dev)
+    V.vlasov_valu_probe(vbuf, 200, stream)
+    ve = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ve[0].record(stream)
+    ops = 0.0
+    for _ in range(3):
+        ops += V.vlasov_valu_probe(vbuf, 2000, stream)
+    ve[1].record(stream)
+    torch.cuda.synchronize()
+    valu_probe = ops / (ve[0].elapsed_time(ve[1]) * 1e-3) / 1e12
+    del vbuf
+    _log(f"bench: VALU probe {valu_probe:.1f} Tlane-op/s")
 
     r = timed_run(V, torch, inputs, w, grid, prec, K, W, dev, stream)
     total_ms, step_ms, per = r["total_ms"], r["step_ms"], r["per"]
@@ -433,11 +470,14 @@ def main():
     launch_bytes = bpc * w.cells
     achieved_gbs = launch_bytes / (avg[dominant] * 1e-3) / 1e9
     traffic = measured_traffic(prec, dominant, w.nu[0], w.n[0])
-    # Every launch streams f once in and once out: the roofline is HBM.  The
-    # fused kick does three sweeps of arithmetic per round trip, so its
-    # fraction of the HBM peak also shows how far its ALU work is from hiding
-    # behind the memory traffic.
-    roofline = {
+    # Every launch streams f once in and once out (HBM), and evaluates the flux
+    # of every interface (vector ALU).  Both are reported for the slowest
+    # launch; the one it is closer to is its bound.  The ALU side counts VALU
+    # lane-operations (rocprofv3 SQ_INSTS_VALU x 64 per dispatch, committed
+    # summary, guarded by the kernel sources' hash): the early-out of the
+    # limiter makes the work per cell data-dependent, so the count, not a
+    # fixed formula, is the arithmetic the launch does.
+    hbm = {
         "bound": "hbm",
         "kernel": "kick (ux, uy, uz fused)" if dominant == "kick" else f"sweep {dominant}",
         "bytes_per_launch": launch_bytes,
@@ -448,6 +488,25 @@ def main():
         "traffic": traffic,
         "frac_of_copy_probe": achieved_gbs / copy_gbs,
     }
+    roofline = hbm
+    lane_ops = measured_valu(prec, dominant, w.nu[0], w.n[0])
+    if lane_ops is not None:
+        valu_t = lane_ops / (avg[dominant] * 1e-3) / 1e12
+        alu = {
+            "bound": "alu",
+            "kernel": hbm["kernel"],
+            "lane_ops_per_launch": lane_ops,
+            "achieved": valu_t,
+            "peak": VALU_PEAK_TLANE_OPS,
+            "unit": "Tlane-op/s",
+            "frac": valu_t / VALU_PEAK_TLANE_OPS,
+            "traffic": traffic,
+            "frac_of_valu_probe": valu_t / valu_probe,
+        }
+        if alu["frac"] > hbm["frac"]:
+            roofline = dict(alu, hbm={k: v for k, v in hbm.items() if k not in ("bound", "kernel")})
+        else:
+            roofline = dict(hbm, alu={k: v for k, v in alu.items() if k not in ("bound", "kernel")})
     _log("bench: per-kernel ms " + json.dumps({k: round(v, 3) for k, v in avg.items()}))
     for nm in per:
         _log(f"bench: {nm} ms per step " + " ".join(f"{x:.2f}" for x in per_step(per, nm, K)))
@@ -464,6 +523,8 @@ def main():
         "warmup": W,
         "ms_per_step": total_ms / K,
         "median_ms_per_step": statistics.median(step_ms),
+        "min_ms_per_step": min(step_ms),
+        "max_ms_per_step": max(step_ms),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -486,6 +547,7 @@ def main():
         "kernel_ms_per_step": {k: [round(x, 3) for x in per_step(per, k, K)]
                                for k in per},
         "copy_probe_gbs": copy_gbs,
+        "valu_probe_tlane_ops": valu_probe,
         "roofline": roofline,
     }
     if args.prec == "f32" and not args.no_fp16:

@@ -471,6 +471,14 @@ int vlasov_sum_f64(const double* x, int64_t n, double* out, void* stream);
  * Not part of the method. */
 int vlasov_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 
+/* Vector-ALU probe: n threads (n a positive multiple of 256) each run eight
+ * independent chains of FP32 FMA, med3, min3, max3, add and mul for `iters`
+ * iterations and write one float to out[0..n) (device memory of n floats,
+ * caller-owned).  *lane_ops (host pointer) receives the lane-operations
+ * launched, 64 n iters, so that the kernel's time gives the issue rate the
+ * sweeps' arithmetic can reach.  Not part of the method. */
+int vlasov_valu_probe(float* out, int64_t n, int iters, double* lane_ops, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

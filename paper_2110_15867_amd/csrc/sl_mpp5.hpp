@@ -222,14 +222,14 @@ __device__ __forceinline__ float med3(float a, float b, float c)
 }
 
 // minmod(4Da-Db, 4Db-Da, Da, Db): least magnitude when all four share a
-// strict sign, else 0 -- as med3(min, max, 0).
+// strict sign, else 0.  The two-argument minmod is med3(x, y, 0), and the
+// four-argument one is the minmod of two such pairs: three medians, no
+// min/max (whose operands the compiler would first have to canonicalise).
 __device__ __forceinline__ float curv_minmod(float Da, float Db)
 {
     const float p = fmaf(4.0f, Da, -Db);
     const float q = fmaf(4.0f, Db, -Da);
-    const float mn = fminf(fminf(p, q), fminf(Da, Db));
-    const float mx = fmaxf(fmaxf(p, q), fmaxf(Da, Db));
-    return med3(mn, mx, 0.0f);
+    return med3(med3(p, q, 0.0f), med3(Da, Db, 0.0f), 0.0f);
 }
 
 __device__ __forceinline__ float curvature(float l, float c, float r)

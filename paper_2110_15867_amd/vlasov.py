@@ -114,6 +114,8 @@ def _load():
     L.vlasov_sum_f64.argtypes = [P, ctypes.c_int64, P, P]
     L.vlasov_stream_copy.restype = I
     L.vlasov_stream_copy.argtypes = [P, P, S, P]
+    L.vlasov_valu_probe.restype = I
+    L.vlasov_valu_probe.argtypes = [P, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_double), P]
     L.vlasov_field_noalloc_max_bytes.restype = S
     L.vlasov_field_noalloc_max_bytes.argtypes = []
     L.vlasov_field_noalloc.restype = I
@@ -355,6 +357,14 @@ def vlasov_encode(grid, prec, f32, codes, scale, stream=None):
 def vlasov_decode(grid, prec, codes, scale, f32, stream=None):
     _check(_lib.vlasov_decode(ctypes.byref(grid), int(prec), _ptr(codes), _ptr(scale), _ptr(f32),
                               _stream(stream)), "vlasov_decode")
+
+
+def vlasov_valu_probe(out, iters, stream=None) -> float:
+    """Launch the VALU probe over out.numel() threads; returns the lane-operations."""
+    ops = ctypes.c_double(0.0)
+    _check(_lib.vlasov_valu_probe(_ptr(out), int(out.numel()), int(iters), ctypes.byref(ops),
+                                  _stream(stream)), "vlasov_valu_probe")
+    return ops.value
 
 
 def vlasov_stream_copy(src, dst, nbytes, stream=None):
