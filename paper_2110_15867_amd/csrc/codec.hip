@@ -54,7 +54,7 @@ __global__ void __launch_bounds__(256) k_decode(const typename Codec<P>::T* __re
     const float sc = scale[t / G];
     Pack<float, 4> v;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) v.v[k] = Codec<P>::dec(q.v[k]) * sc;
+    for (int k = 0; k < 4; ++k) v.v[k] = decode<P>(q.v[k], sc);
     *reinterpret_cast<Pack<float, 4>*>(f + 4 * t) = v;
 }
 

@@ -75,7 +75,7 @@ struct BlockSlots {
             float* dst = lds + (e / NU) * (NU + 1) + e % NU;
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                dst[u] = Codec<P>::scaled ? Codec<P>::dec(q[s].v[u]) * sc[s] : Codec<P>::dec(q[s].v[u]);
+                dst[u] = decode<P>(q[s].v[u], sc[s]);
         }
     }
 };
@@ -366,8 +366,7 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
                 double s0 = 0.0, sz = 0.0;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const double xv = (double)(Codec<P>::scaled ? Codec<P>::dec(q.v[u]) * sc
-                                                                 : Codec<P>::dec(q.v[u]));
+                    const double xv = (double)decode<P>(q.v[u], sc);
                     const double uz = a.umin[2] + ((double)(jz + u) + 0.5) * a.du[2];
                     s0 += xv;
                     sz = fma(uz, xv, sz);

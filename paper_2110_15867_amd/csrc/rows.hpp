@@ -227,7 +227,7 @@ struct URowReader {
         const Pack<T, V> q = buffer_load_pack<T, V>(row_rsrc(base + (long)phys * stride, nbytes), loff);
 #pragma unroll
         for (int v = 0; v < V; ++v)
-            x[v] = Codec<P>::scaled ? Codec<P>::dec(q.v[v]) * sc : Codec<P>::dec(q.v[v]);
+            x[v] = decode<P>(q.v[v], sc);
         phys += dir;
         if (phys == M) phys = 0;
         else if (phys < 0) phys = M - 1;
@@ -328,12 +328,8 @@ struct PairRowReader {
             sc = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
                      row_rsrc(sbase + (long)phys * sstride, sbytes), (int)soff, 0, 0));
         const Pack<T, 2> q = buffer_load_pack<T, 2>(row_rsrc(base + (long)phys * stride, nbytes), off);
-        float v0 = Codec<P>::dec(q.v[0]);
-        float v1 = Codec<P>::dec(q.v[1]);
-        if (Codec<P>::scaled) {
-            v0 *= sc;
-            v1 *= sc;
-        }
+        const float v0 = decode<P>(q.v[0], sc);
+        const float v1 = decode<P>(q.v[1], sc);
         const float p0 = xor_half<H>(v0);
         const float p1 = xor_half<H>(v1);
         x[0] = lo ? p0 : v1;          // upper half: line A

@@ -86,13 +86,28 @@ __device__ __forceinline__ typename Codec<P>::T quantize(float x, float inv)
     return Codec<P>::enc(y);
 }
 
+// Value of code q with scale sc: the product code x scale, written as an FMA
+// with -0 (which adds nothing, so the sign of a zero product survives) so
+// that FP16 codes decode in one mixed-precision FMA (the FP16 operand is
+// widened inside the instruction, exactly).  Every kernel decodes with it.
+template <int P>
+__device__ __forceinline__ float decode(typename Codec<P>::T q, float sc)
+{
+    if (!Codec<P>::scaled) return Codec<P>::dec(q);
+    // (the -0 is hidden from the optimiser, which would otherwise turn the
+    // FMA back into a widening and a multiply)
+    float nz = -0.0f;
+    asm("" : "+v"(nz));
+    return fmaf(Codec<P>::dec(q), sc, nz);
+}
+
 template <int P, int V>
 __device__ __forceinline__ void load_row(const typename Codec<P>::T* p, float scale, float* x)
 {
     using T = typename Codec<P>::T;
     Pack<T, V> q = *reinterpret_cast<const Pack<T, V>*>(p);
 #pragma unroll
-    for (int v = 0; v < V; ++v) x[v] = Codec<P>::scaled ? Codec<P>::dec(q.v[v]) * scale : Codec<P>::dec(q.v[v]);
+    for (int v = 0; v < V; ++v) x[v] = decode<P>(q.v[v], scale);
 }
 
 template <int P, int V>
