@@ -2,10 +2,12 @@
 in the launch configuration bench.py times: kick, z, y, x, kick through the
 public single-launch calls, FP32 and FP16 storage.
 
-After each launch, sampled outputs that the oracle computes one at a time:
-whole velocity blocks of sampled spatial cells for the kicks (the oracle's
-three velocity sweeps on a one-cell grid with that cell's field), whole
-lines for the drifts (the oracle's line sweep with the line's shift).  Over
+After each launch, sampled outputs that the oracle computes piece by piece:
+whole velocity blocks of 32 sampled spatial cells for the kicks (the
+oracle's three velocity sweeps on a one-cell grid with that cell's field),
+and for the drifts 4 whole spatial lines along the drift axis with every
+velocity cell of them (2.1e6 cells each: the oracle's sweep on a grid of
+that one line, whose cell width and shifts are the full grid's).  Over
 the whole array: positivity, and mass plus the velocity-face outflow kept
 (FP64 moments).  FP32 is held to the sweeps' bar (1e-5 of max f per
 launch); FP16 to its output codes' rounding plus that bar.
@@ -44,17 +46,20 @@ def _block_scales(st, idx):
     return np.stack([st.scale[c].double().cpu().numpy() for c in idx])
 
 
-def _line(st, axis, ix, jx):
-    """FP64 line along spatial axis `axis` through spatial index ix and velocity index jx
-    (ix, jx tuples; ix[axis] ignored), with the scales of its elements."""
+def _bundle(st, axis, ix):
+    """FP64 values of the spatial line along `axis` through ix (ix[axis]
+    ignored) with its whole velocity blocks, shaped as a one-line 6D grid,
+    and the scales broadcast to it (None for FP32)."""
     sl = list(ix)
     sl[axis] = slice(None)
-    sel = tuple(sl) + tuple(jx)
-    x = st.f[sel].double()
+    x = st.f[tuple(sl)].double()                     # [n_axis][jx][jy][jz]
+    shape = [1, 1, 1]
+    shape[axis] = x.shape[0]
     if st.prec == V.F32:
-        return x.cpu().numpy(), None
-    sc = st.scale[tuple(sl) + tuple(jx[:2])].double()
-    return (x * sc).cpu().numpy(), sc.cpu().numpy()
+        return x.cpu().numpy().reshape(tuple(shape) + x.shape[1:]), None
+    sc = st.scale[tuple(sl)].double()[..., None]     # [n_axis][jx][jy][1]
+    return ((x * sc).cpu().numpy().reshape(tuple(shape) + x.shape[1:]),
+            sc.expand_as(x).cpu().numpy().reshape(tuple(shape) + x.shape[1:]))
 
 
 @pytest.mark.parametrize("prec", [V.F32, V.F16])
@@ -79,7 +84,7 @@ def test_full_size_step_sampled_against_oracle(prec):
     mass0 = float(mass0)
     fmax = float(cur.f.float().abs().max()) * (1.0 if prec == V.F32 else float(cur.scale.max()))
     bar = 1e-5 * fmax
-    cells = [tuple(int(v) for v in rng.integers(0, w.n[0], 3)) for _ in range(4)]
+    cells = [tuple(int(v) for v in rng.integers(0, w.n[0], 3)) for _ in range(32)]
     for step, name in enumerate(["kick", "z", "y", "x", "kick"]):
         out = V.empty_state(grid, prec, "cuda")
         if name == "kick":
@@ -102,15 +107,18 @@ def test_full_size_step_sampled_against_oracle(prec):
             getattr(V, f"vlasov_advect_{name}")(grid, prec, cur.f, cur.scale, out.f, out.scale,
                                                 w.dt)
             torch.cuda.synchronize()
-            for _ in range(12):
+            n1 = [1, 1, 1]
+            n1[axis] = w.n[axis]
+            L1 = [1.0, 1.0, 1.0]
+            L1[axis] = w.L[axis]
+            og_line = oracle.Grid.make(tuple(n1), w.nu, tuple(L1), w.umax)
+            for _ in range(4):
                 ix = tuple(int(v) for v in rng.integers(0, w.n[0], 3))
-                jx = tuple(int(v) for v in rng.integers(0, w.nu[0], 3))
-                line_in, _ = _line(cur, axis, ix, jx)
-                line_out, sc_out = _line(out, axis, ix, jx)
-                s = oracle.position_shift(og, axis, jx[axis], w.dt)
-                want, _ = oracle.sweep_line(line_in, s, periodic=True)
+                b_in, _ = _bundle(cur, axis, ix)
+                b_out, sc_out = _bundle(out, axis, ix)
+                want = oracle.advect_position(og_line, axis, b_in, w.dt)
                 tol = bar if sc_out is None else bar + 1.01 * HALF_ULP[prec] * sc_out
-                assert np.all(np.abs(line_out - want) <= tol), (name, ix, jx)
+                assert np.all(np.abs(b_out - want) <= tol), (name, ix)
         del cur
         cur = out
     # whole array: positivity; mass plus what left through the velocity faces
