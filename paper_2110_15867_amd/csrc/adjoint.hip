@@ -83,62 +83,110 @@ __device__ __forceinline__ Lin lin_comb(float p, const Lin& x, float q, const Li
     return r;
 }
 
-// Selections with the oracle's tie rules, on (value, form) pairs.
+// A value with its linear form.
 struct VL {
     float v;
     Lin l;
 };
-__device__ __forceinline__ VL vmin2(const VL& x, const VL& y) { return x.v <= y.v ? x : y; }
-__device__ __forceinline__ VL vmax2(const VL& x, const VL& y) { return x.v >= y.v ? x : y; }
-__device__ __forceinline__ VL vmed3(const VL& x, const VL& y, const VL& z)
-{
-    return vmax2(vmin2(x, y), vmin2(vmax2(x, y), z));
-}
-__device__ __forceinline__ VL vminmod4(const VL& w, const VL& x, const VL& y, const VL& z)
-{
-    if (w.v > 0.0f && x.v > 0.0f && y.v > 0.0f && z.v > 0.0f)
-        return vmin2(vmin2(w, x), vmin2(y, z));
-    if (w.v < 0.0f && x.v < 0.0f && y.v < 0.0f && z.v < 0.0f)
-        return vmax2(vmax2(w, x), vmax2(y, z));
-    return VL{0.0f, lin_zero()};
-}
-
 struct FluxLin {
-    float phi;      // flux magnitude (identical to flux_mag)
     float W[5];     // d phi / d (a..e)
     float dmu;      // d phi / d mu
 };
 
+// Selections on (value, candidate index) pairs with the FP64 oracle's tie
+// rules (min and max keep their first argument on a tie; the median is
+// max(min(x,y), min(max(x,y),z))): every selection is decided on the
+// values, and the linear form is built for the winning candidate only.
+struct Pick {
+    float v;
+    int id;
+};
+__device__ __forceinline__ Pick pmin2(const Pick& x, const Pick& y) { return x.v <= y.v ? x : y; }
+__device__ __forceinline__ Pick pmax2(const Pick& x, const Pick& y) { return x.v >= y.v ? x : y; }
+__device__ __forceinline__ Pick pmed3(const Pick& x, const Pick& y, const Pick& z)
+{
+    return pmax2(pmin2(x, y), pmin2(pmax2(x, y), z));
+}
+// minmod of four; id 4 stands for the zero it returns when signs differ
+__device__ __forceinline__ Pick pminmod4(const Pick& w, const Pick& x, const Pick& y, const Pick& z)
+{
+    if (w.v > 0.0f && x.v > 0.0f && y.v > 0.0f && z.v > 0.0f)
+        return pmin2(pmin2(w, x), pmin2(y, z));
+    if (w.v < 0.0f && x.v < 0.0f && y.v < 0.0f && z.v < 0.0f)
+        return pmax2(pmax2(w, x), pmax2(y, z));
+    return Pick{0.0f, 4};
+}
+
+// Form of the curvature minmod that won: candidates 4 Da - Db (0),
+// 4 Db - Da (1), Da (2), Db (3), zero (4).
+__device__ __forceinline__ Lin minmod_form(int id, const Lin& Da, const Lin& Db)
+{
+    switch (id) {
+        case 0: return lin_comb(4.0f, Da, -1.0f, Db);
+        case 1: return lin_comb(4.0f, Db, -1.0f, Da);
+        case 2: return Da;
+        case 3: return Db;
+        default: return lin_zero();
+    }
+}
+
+__device__ __forceinline__ Lin curvature_form(const Lin& l, const Lin& m, const Lin& r)
+{
+    return lin_comb(1.0f, lin_comb(1.0f, l, -2.0f, m), 1.0f, r);
+}
+
 // mp_bounded on (value, form) pairs: the values with mp_bounded's FP32
 // operations, so every selection is the forward's.  u[] are the forms of the
 // stencil's a..e (the upwind frame's cells, or mirrored for a comp line);
-// the upper-limit factor alpha carries its mu-derivative alpha_mu.
+// the upper-limit factor alpha carries its mu-derivative alpha_mu.  The
+// candidates of the bounds are c (0), d (1), fMD (2), fUL (3), fLC (4) and
+// the unlimited value fhat (5).
 __device__ VL mp_bounded_lin(const VL& fhat, const Stencil& s, const Lin (&u)[5], float alpha,
                              float alpha_mu)
 {
     const float Dmv = s.dm1 - s.dm2, D0v = s.d0 - s.dm1, Dpv = s.dp1 - s.d0;
-    const Lin cb = lin_comb(1.0f, u[2], -1.0f, u[1]);                       // c - b
-    const VL Dm{Dmv, lin_comb(1.0f, lin_comb(1.0f, u[0], -2.0f, u[1]), 1.0f, u[2])};
-    const VL D0{D0v, lin_comb(1.0f, lin_comb(1.0f, u[1], -2.0f, u[2]), 1.0f, u[3])};
-    const VL Dp{Dpv, lin_comb(1.0f, lin_comb(1.0f, u[2], -2.0f, u[3]), 1.0f, u[4])};
     // curv_minmod(Da, Db) = minmod(4Da-Db, 4Db-Da, Da, Db)
-    const VL p1{fmaf(4.0f, D0v, -Dpv), lin_comb(4.0f, D0.l, -1.0f, Dp.l)};
-    const VL q1{fmaf(4.0f, Dpv, -D0v), lin_comb(4.0f, Dp.l, -1.0f, D0.l)};
-    const VL Mp = vminmod4(p1, q1, D0, Dp);
-    const VL p2{fmaf(4.0f, Dmv, -D0v), lin_comb(4.0f, Dm.l, -1.0f, D0.l)};
-    const VL q2{fmaf(4.0f, D0v, -Dmv), lin_comb(4.0f, D0.l, -1.0f, Dm.l)};
-    const VL Mm = vminmod4(p2, q2, Dm, D0);
-    const VL c{s.c, u[2]};
-    const VL d{s.d, u[3]};
-    VL fUL{fmaf(alpha, s.dm1, s.c), lin_comb(alpha, cb, 1.0f, u[2])};
-    fUL.l.w[5] += alpha_mu * s.dm1;
-    const VL fMD{0.5f * ((s.c + s.d) - Mp.v),
-                 lin_comb(0.5f, lin_comb(1.0f, u[2], 1.0f, u[3]), -0.5f, Mp.l)};
-    const VL fLC{fmaf(4.0f / 3.0f, Mm.v, fmaf(0.5f, s.dm1, s.c)),
-                 lin_comb(4.0f / 3.0f, Mm.l, 1.0f, lin_comb(0.5f, cb, 1.0f, u[2]))};
-    const VL lo = vmax2(vmin2(vmin2(c, d), fMD), vmin2(vmin2(c, fUL), fLC));
-    const VL hi = vmin2(vmax2(vmax2(c, d), fMD), vmax2(vmax2(c, fUL), fLC));
-    return vmed3(fhat, lo, hi);
+    const Pick Mp = pminmod4(Pick{fmaf(4.0f, D0v, -Dpv), 0}, Pick{fmaf(4.0f, Dpv, -D0v), 1},
+                             Pick{D0v, 2}, Pick{Dpv, 3});
+    const Pick Mm = pminmod4(Pick{fmaf(4.0f, Dmv, -D0v), 0}, Pick{fmaf(4.0f, D0v, -Dmv), 1},
+                             Pick{Dmv, 2}, Pick{D0v, 3});
+    const Pick c{s.c, 0};
+    const Pick d{s.d, 1};
+    const Pick fMD{0.5f * ((s.c + s.d) - Mp.v), 2};
+    const Pick fUL{fmaf(alpha, s.dm1, s.c), 3};
+    const Pick fLC{fmaf(4.0f / 3.0f, Mm.v, fmaf(0.5f, s.dm1, s.c)), 4};
+    const Pick lo = pmax2(pmin2(pmin2(c, d), fMD), pmin2(pmin2(c, fUL), fLC));
+    const Pick hi = pmin2(pmax2(pmax2(c, d), fMD), pmax2(pmax2(c, fUL), fLC));
+    const Pick r = pmed3(Pick{fhat.v, 5}, lo, hi);
+    VL out;
+    out.v = r.v;
+    switch (r.id) {
+        case 5: out.l = fhat.l; break;
+        case 0: out.l = u[2]; break;
+        case 1: out.l = u[3]; break;
+        case 3: {
+            const Lin cb = lin_comb(1.0f, u[2], -1.0f, u[1]);                 // c - b
+            out.l = lin_comb(alpha, cb, 1.0f, u[2]);
+            out.l.w[5] += alpha_mu * s.dm1;
+            break;
+        }
+        case 2: {
+            const Lin D0 = curvature_form(u[1], u[2], u[3]);
+            const Lin Dp = curvature_form(u[2], u[3], u[4]);
+            out.l = lin_comb(0.5f, lin_comb(1.0f, u[2], 1.0f, u[3]), -0.5f,
+                             minmod_form(Mp.id, D0, Dp));
+            break;
+        }
+        default: {
+            const Lin cb = lin_comb(1.0f, u[2], -1.0f, u[1]);
+            const Lin Dm = curvature_form(u[0], u[1], u[2]);
+            const Lin D0 = curvature_form(u[1], u[2], u[3]);
+            out.l = lin_comb(4.0f / 3.0f, minmod_form(Mm.id, Dm, D0), 1.0f,
+                             lin_comb(0.5f, cb, 1.0f, u[2]));
+            break;
+        }
+    }
+    return out;
 }
 
 // The forward flux with its frozen linearisation.  The values follow
@@ -165,13 +213,7 @@ __device__ FluxLin flux_lin(const Stencil& s, const LineShift& sh, const WeightS
     Y.l.w[5] = ydmu;
     const Lin uc = lin_unit(2);
     const bool early = med3(y, 0.0f, m) == y;
-    const VL zero{0.0f, lin_zero()};
-    const VL C{s.c, uc};
     FluxLin out;
-    // the value: flux_mag's own operations
-    float pre_v = sh.mu * (s.c + y);
-    if (!early) pre_v = mp_flux<true>(s, sh, y);
-    out.phi = med3(pre_v, 0.0f, s.c);
     VL r;
     if (!sh.comp) {
         VL F{s.c + y, lin_comb(1.0f, uc, 1.0f, Y.l)};
@@ -184,7 +226,9 @@ __device__ FluxLin flux_lin(const Stencil& s, const LineShift& sh, const WeightS
         // positivity clamp med3(mu L, 0, c), oracle tie rules
         VL pre{sh.mu * F.v, lin_comb(sh.mu, F.l, 0.0f, F.l)};
         pre.l.w[5] = fmaf(sh.mu, F.l.w[5], F.v);
-        r = vmed3(pre, zero, C);
+        const Pick k = pmed3(Pick{pre.v, 0}, Pick{0.0f, 1}, Pick{s.c, 2});
+        r.v = k.v;
+        r.l = k.id == 0 ? pre.l : (k.id == 1 ? lin_zero() : uc);
     } else {
         // complement: ghat = c - q y on the mirrored stencil with alpha_c; what
         // leaves through the complement side is Psi = med3(mu' ghat_lim, 0, c)
@@ -204,9 +248,10 @@ __device__ FluxLin flux_lin(const Stencil& s, const LineShift& sh, const WeightS
         }
         VL P{sh.muc * G.v, lin_comb(sh.muc, G.l, 0.0f, G.l)};
         P.l.w[5] = sh.muc * G.l.w[5] - G.v;
-        const VL psi = vmed3(P, zero, C);
-        r.v = s.c - psi.v;
-        r.l = lin_comb(1.0f, uc, -1.0f, psi.l);
+        const Pick k = pmed3(Pick{P.v, 0}, Pick{0.0f, 1}, Pick{s.c, 2});
+        const Lin psi = k.id == 0 ? P.l : (k.id == 1 ? lin_zero() : uc);
+        r.v = s.c - k.v;
+        r.l = lin_comb(1.0f, uc, -1.0f, psi);
     }
 #pragma unroll
     for (int q = 0; q < 5; ++q) out.W[q] = r.l.w[q];
@@ -261,10 +306,14 @@ __device__ void line_tangent(Reader32& rx, Reader32& rv, float* out, long stride
 // Adjoint of one line: x = forward input, lam = output adjoint (frame rows
 // read through rl, which starts N rows later).  Writes lam_in and returns
 // lam_mu.  R: a row reader of global memory (Reader32) or of an LDS tile.
-template <class R>
-__device__ float line_adjoint(R& rx, R& rl, float* lam_in, long stride, int M, int dir,
+template <int MT, class R>
+__device__ float line_adjoint(R& rx, R& rl, float* lam_in, long stride, int Mrt, int dir,
                               const LineShift& sh, bool periodic)
 {
+    // MT > 0: the line length at compile time (the walk itself stays a loop:
+    // unrolled, its inlined linearisations need more registers than a SIMD
+    // has for two waves)
+    const int M = MT > 0 ? MT : Mrt;
     const WeightSlopes ds = sl5_weight_slopes(sh.mu);
     const int N = sh.N;
     // interfaces j = -2 .. M+1 ; interface j reads x_{j-2..j+2}, psi_j needs
@@ -281,6 +330,7 @@ __device__ float line_adjoint(R& rx, R& rl, float* lam_in, long stride, int M, i
     // identity term source: lam_{r+N} for r = j-2 -> read separately
     R rid = rl;
     rid.seek(N);                                     // lam_{0+N}
+#pragma unroll 1
     for (int j = -2; j <= M + 1; ++j) {
         if (j > -2) {
             for (int q = 0; q < 4; ++q) wx[q] = wx[q + 1];
@@ -333,6 +383,7 @@ __global__ void __launch_bounds__(256) k_position_tan(const float* __restrict__ 
     line_tangent(rx, rv, out + base, a.I, a.M, dir, sh, true, 0.0f);
 }
 
+template <int MT>
 __global__ void __launch_bounds__(256) k_position_adj(const float* __restrict__ f,
                                                       const float* __restrict__ lam,
                                                       float* __restrict__ lam_in, PosArgs a)
@@ -346,7 +397,7 @@ __global__ void __launch_bounds__(256) k_position_adj(const float* __restrict__ 
     const long base = o * (long)a.M * a.I + k;
     Reader32 rx{f + base, nullptr, a.I, 0, a.M, dir, true, 0};
     Reader32 rl{lam + base, nullptr, a.I, 0, a.M, dir, true, 0};
-    line_adjoint(rx, rl, lam_in + base, a.I, a.M, dir, sh, true);
+    line_adjoint<MT>(rx, rl, lam_in + base, a.I, a.M, dir, sh, true);
 }
 
 // Velocity sweeps: one work-group per spatial cell; lines of the cell are
@@ -373,6 +424,7 @@ __global__ void __launch_bounds__(256) k_velocity_tan(const float* __restrict__ 
     }
 }
 
+template <int MT>
 __global__ void __launch_bounds__(256) k_velocity_adj(const float* __restrict__ f,
                                                       const float* __restrict__ lam,
                                                       float* __restrict__ lam_in,
@@ -390,7 +442,7 @@ __global__ void __launch_bounds__(256) k_velocity_adj(const float* __restrict__ 
         const long base = ((cell * a.nsub + sub) * a.M) * a.I + k;
         Reader32 rx{f + base, nullptr, a.I, 0, a.M, dir, a.periodic, 0};
         Reader32 rl{lam + base, nullptr, a.I, 0, a.M, dir, a.periodic, 0};
-        mine += (double)line_adjoint(rx, rl, lam_in + base, a.I, a.M, dir, sh, a.periodic);
+        mine += (double)line_adjoint<MT>(rx, rl, lam_in + base, a.I, a.M, dir, sh, a.periodic);
     }
     if (lam_g != nullptr) {
         const double tot = block_sum(mine, red);
@@ -437,7 +489,7 @@ __global__ void __launch_bounds__(NT) k_velocity_adj_uz(const float* __restrict_
         if (threadIdx.x < nl) {
             LdsReader rx{tf + threadIdx.x * LS, 1, MT, dir, a.periodic, 0};
             LdsReader rl{tl + threadIdx.x * LS, 1, MT, dir, a.periodic, 0};
-            mine += (double)line_adjoint(rx, rl, to + threadIdx.x * LS, 1, MT, dir, sh,
+            mine += (double)line_adjoint<MT>(rx, rl, to + threadIdx.x * LS, 1, MT, dir, sh,
                                          a.periodic);
         }
         __syncthreads();
@@ -470,8 +522,13 @@ hipError_t launch_position_adj(const float* f, const float* lam, float* lam_in, 
 {
     const long total = a.O * a.I;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_position_adj, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, f,
-                       lam, lam_in, a);
+    const dim3 grid((unsigned)((total + 255) / 256));
+    switch (a.M) {
+        case 16: hipLaunchKernelGGL(k_position_adj<16>, grid, dim3(256), 0, st, f, lam, lam_in, a); break;
+        case 32: hipLaunchKernelGGL(k_position_adj<32>, grid, dim3(256), 0, st, f, lam, lam_in, a); break;
+        case 64: hipLaunchKernelGGL(k_position_adj<64>, grid, dim3(256), 0, st, f, lam, lam_in, a); break;
+        default: hipLaunchKernelGGL(k_position_adj<0>, grid, dim3(256), 0, st, f, lam, lam_in, a); break;
+    }
     return hipGetLastError();
 }
 
@@ -513,8 +570,13 @@ hipError_t launch_velocity_adj(const float* f, const float* lam, float* lam_in, 
                 break;
         }
     }
-    hipLaunchKernelGGL(k_velocity_adj, dim3((unsigned)a.cells), dim3(vel_block(a)), 0, st, f,
-                       lam, lam_in, lam_g, a);
+    const dim3 cg((unsigned)a.cells), cb(vel_block(a));
+    switch (a.M) {
+        case 16: hipLaunchKernelGGL(k_velocity_adj<16>, cg, cb, 0, st, f, lam, lam_in, lam_g, a); break;
+        case 32: hipLaunchKernelGGL(k_velocity_adj<32>, cg, cb, 0, st, f, lam, lam_in, lam_g, a); break;
+        case 64: hipLaunchKernelGGL(k_velocity_adj<64>, cg, cb, 0, st, f, lam, lam_in, lam_g, a); break;
+        default: hipLaunchKernelGGL(k_velocity_adj<0>, cg, cb, 0, st, f, lam, lam_in, lam_g, a); break;
+    }
     return hipGetLastError();
 }
 
