@@ -404,6 +404,135 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
     }
 }
 
+// ---------------------------------------------------------------------------
+// uz sweep of long lines (nu_z = 64: a 64^3 FP32 block is 1 MiB, too large
+// for the fused kick): a work-group of 256 threads walks one cell's 4096
+// uz-lines in 16 tiles of 256 whole lines in LDS (padded to 65 floats), one
+// line per thread with kick_axis_dir, while the tile after next is on its
+// way from HBM into registers -- the kick's structure for one axis.  Loads
+// and stores are 16-byte groups of consecutive values, so every access is
+// coalesced; each thread owns a whole uz-line, so its new scale needs no
+// reduction across lanes.  The line outflows are summed per thread over the
+// cell's tiles, then over the work-group in a fixed order.
+// ---------------------------------------------------------------------------
+template <int P, int NU>
+struct TileSlots {
+    using T = typename Codec<P>::T;
+    static constexpr int NT = 256;               // threads = lines per tile
+    static constexpr int NS = NT * NU / (NT * 4); // 4-value groups per thread
+    Pack<T, 4> q[NS];
+    float sc[NS];
+    __device__ static int elem(int s, int t) { return (s * NT + t) * 4; }
+    __device__ void load(const T* __restrict__ src, const float* __restrict__ ssrc, int t)
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int e = elem(s, t);
+            q[s] = *reinterpret_cast<const Pack<T, 4>*>(src + e);
+            sc[s] = Codec<P>::scaled ? ssrc[e / NU] : 1.0f;
+        }
+    }
+    __device__ void put(float* lds, int t) const
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int e = elem(s, t);
+            float* dst = lds + (e / NU) * (NU + 1) + e % NU;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dst[u] = decode<P>(q[s].v[u], sc[s]);
+        }
+    }
+};
+
+template <int P, int NU, bool PER>
+__global__ void __launch_bounds__(256) k_vel_uz_tiles(const typename Codec<P>::T* __restrict__ fin,
+                                                     const float* __restrict__ sin,
+                                                     typename Codec<P>::T* __restrict__ fout,
+                                                     float* __restrict__ sout, VelArgs a)
+{
+    using T = typename Codec<P>::T;
+    using Slots = TileSlots<P, NU>;
+    constexpr int NT = Slots::NT;
+    constexpr int NTILE = NU * NU / NT;          // tiles per cell
+    constexpr int TE = NT * NU;                  // values per tile
+    extern __shared__ float lds[];
+    __shared__ float lmax[Codec<P>::scaled ? NT : 1];
+    __shared__ double red[NT / 64];
+    const int t = threadIdx.x;
+    const long cell = blockIdx.x;
+    const LineShift sh = split_shift((double)a.g[cell] * a.factor, NU, PER);
+    const int N = uniform_sgpr(sh.N);
+    const bool neg = uniform_sgpr(sh.neg ? 1 : 0) != 0;
+    const T* src = fin + cell * (long)NU * NU * NU;
+    const float* ssrc = sin + cell * (long)NU * NU;
+    T* dst = fout + cell * (long)NU * NU * NU;
+    float* sdst = sout + cell * (long)NU * NU;
+
+    Slots R;
+    R.load(src, ssrc, fresh_tid());
+    R.put(lds, fresh_tid());
+    R.load(src + TE, ssrc + NT, fresh_tid());
+    __syncthreads();
+    float ofl = 0.0f;
+    for (int k = 0; k < NTILE; ++k) {
+        float* line = lds + t * (NU + 1);
+        float* sl = Codec<P>::scaled ? sdst + k * NT + t : nullptr;
+        ofl += neg ? kick_axis_dir<P, NU, PER, 2, true>(line, sh, N, sl, lmax + t)
+                   : kick_axis_dir<P, NU, PER, 2, false>(line, sh, N, sl, lmax + t);
+        __syncthreads();
+        const int ts = fresh_tid();
+        T* out = dst + (long)k * TE;
+#pragma unroll
+        for (int s = 0; s < Slots::NS; ++s) {
+            const int e = Slots::elem(s, ts);
+            const float* v = lds + (e / NU) * (NU + 1) + e % NU;
+            const float inv = Codec<P>::scaled ? inv_scale(lmax[e / NU]) : 1.0f;
+            Pack<T, 4> q;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q.v[u] = quantize<P>(v[u], inv);
+            *reinterpret_cast<Pack<T, 4>*>(out + e) = q;
+        }
+        __syncthreads();
+        if (k + 1 < NTILE) {
+            R.put(lds, ts);
+            if (k + 2 < NTILE) R.load(src + (long)(k + 2) * TE, ssrc + (k + 2) * NT, fresh_tid());
+        }
+        __syncthreads();
+    }
+    if (a.outflow != nullptr && !PER) {
+        const double tot = block_sum((double)ofl, red);
+        if (t == 0) a.outflow[cell] += tot * a.du3;
+    }
+}
+
+template <int P>
+static hipError_t launch_vel_uz64_p(const void* fin, const float* sin, void* fout, float* sout,
+                                    const VelArgs& a, hipStream_t st)
+{
+    using T = typename Codec<P>::T;
+    constexpr int NU = 64;
+    const size_t lds = (size_t)256 * (NU + 1) * sizeof(float);
+    auto kern = a.periodic ? k_vel_uz_tiles<P, NU, true> : k_vel_uz_tiles<P, NU, false>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)a.cells), dim3(256), lds, st, (const T*)fin, sin,
+                       (T*)fout, sout, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_vel_uz64(int prec, const void* fin, const float* sin, void* fout, float* sout,
+                           const VelArgs& a, hipStream_t st)
+{
+    if (a.cells == 0) return hipSuccess;
+    if (a.M != 64 || a.nsub != 64 * 64 || a.cells > 0x7fffffffL) return hipErrorInvalidValue;
+    switch (prec) {
+        case PREC_F16: return launch_vel_uz64_p<PREC_F16>(fin, sin, fout, sout, a, st);
+        case PREC_BF16: return launch_vel_uz64_p<PREC_BF16>(fin, sin, fout, sout, a, st);
+        default: return launch_vel_uz64_p<PREC_F32>(fin, sin, fout, sout, a, st);
+    }
+}
+
 // The split of every (cell, axis) shift of a kick, one thread each.
 __global__ void __launch_bounds__(256) k_kick_shifts(KickArgs a, KickShift* __restrict__ tab)
 {

@@ -52,6 +52,9 @@ hipError_t launch_vel_strided(int prec, const void* fin, const float* sin, void*
                               const VelArgs& a, hipStream_t st);
 hipError_t launch_vel_uz(int prec, const void* fin, const float* sin, void* fout, float* sout,
                          const VelArgs& a, hipStream_t st);
+// uz sweep of 64-cell lines through double-buffered LDS tiles (kick.hip)
+hipError_t launch_vel_uz64(int prec, const void* fin, const float* sin, void* fout, float* sout,
+                           const VelArgs& a, hipStream_t st);
 
 // Split shift of one velocity line (uniform over a spatial cell's block):
 // integer part, direction, the fractional part's interface weights in

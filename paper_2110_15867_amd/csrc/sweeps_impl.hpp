@@ -494,6 +494,8 @@ inline hipError_t launch_vel_uz_p(const void* fin, const float* sin, void* fout,
             hipLaunchKernelGGL((k_vel_uz<P, 32, 256>), grid, dim3(256), 0, st, (const T*)fin, sin, (T*)fout, sout, a);
             break;
         case 64:
+            // cubic 64^3 blocks: double-buffered tiles (kick.hip)
+            if (a.nsub == 64 * 64) return launch_vel_uz64(P, fin, sin, fout, sout, a, st);
             hipLaunchKernelGGL((k_vel_uz<P, 64, 128>), grid, dim3(128), 0, st, (const T*)fin, sin, (T*)fout, sout, a);
             break;
         default: {
