@@ -31,6 +31,8 @@ def _grids():
         "nu32": dict(n=(8, 6, 5), nu=(32, 32, 32), L=(1, 2, 10), umax=(1, 1, 1)),
         "long64": dict(n=(64, 3, 64), nu=(4, 6, 64), L=(1, 1, 1), umax=(1, 1, 1)),
         "odd_nuz": dict(n=(5, 4, 3), nu=(8, 6, 6), L=(1, 1, 1), umax=(1, 1, 1)),
+        # cubic 64^3 velocity blocks: the unfused kick's uz tiles
+        "nu64": dict(n=(2, 3, 2), nu=(64, 64, 64), L=(1, 1.5, 1), umax=(1, 1, 1)),
     }
 
 

@@ -31,11 +31,12 @@ def _grid(name):
         "g16": ((6, 5, 7), (8, 12, 16), (1.0, 0.8, 1.3), (1.0, 1.2, 0.9)),
         "g32": ((4, 6, 5), (8, 6, 32), (1.0, 2.0, 3.0), (1.0, 1.0, 1.0)),
         "g64": ((3, 4, 20), (4, 2, 64), (1.0, 1.0, 1.0), (1.0, 1.0, 1.0)),
+        "c64": ((2, 1, 2), (64, 64, 64), (1.0, 1.0, 1.0), (1.0, 1.0, 1.0)),
     }[name]
 
 
 @pytest.mark.parametrize("prec", [V.F16, V.BF16])
-@pytest.mark.parametrize("name", ["g16", "g32", "g64"])
+@pytest.mark.parametrize("name", ["g16", "g32", "g64", "c64"])
 @pytest.mark.parametrize("axis", ["x", "y", "z", "ux", "uy", "uz"])
 def test_sweep_error_within_storage_rounding(prec, name, axis):
     n, nu, L, U = _grid(name)
