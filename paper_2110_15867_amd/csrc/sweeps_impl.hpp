@@ -41,8 +41,11 @@ namespace vlasov {
 // ---------------------------------------------------------------------------
 // Position sweeps
 // ---------------------------------------------------------------------------
+// (at least four work-groups of 256 per CU: the compiler keeps every variant
+// within 128 VGPRs, four waves per SIMD -- the FP16/BF16 y walk with
+// per-lane shifts would otherwise take 144 and run three)
 template <int P, int V, int MT, int GC, bool US, bool MIX>
-__global__ void __launch_bounds__(256) k_position(const typename Codec<P>::T* __restrict__ fin,
+__global__ void __launch_bounds__(256, 4) k_position(const typename Codec<P>::T* __restrict__ fin,
                                                   const float* __restrict__ sin,
                                                   typename Codec<P>::T* __restrict__ fout,
                                                   float* __restrict__ sout, PosArgs a)
