@@ -282,7 +282,8 @@ int run_kick(const vlasov_grid* g, const Dims& d, int prec, int vbc, const void*
 {
     if (!isfinite(dt)) return VLASOV_ERR_NONFINITE;
     int nu[3] = {(int)d.nu[0], (int)d.nu[1], (int)d.nu[2]};
-    if (kick_supported(nu, lds_limit())) {
+    const bool yz64 = kick_yz64_supported(nu, lds_limit());
+    if (kick_supported(nu, lds_limit()) || yz64) {
         KickArgs a;
         memset(&a, 0, sizeof(a));
         a.g = field;
@@ -302,7 +303,16 @@ int run_kick(const vlasov_grid* g, const Dims& d, int prec, int vbc, const void*
             a.umin[k] = -g->umax[k];
             a.du[k] = 2.0 * g->umax[k] / g->nu[k];
         }
-        return from_hip(launch_kick(prec, fin, sin, fout, sout, a, shifts, st));
+        if (!yz64) return from_hip(launch_kick(prec, fin, sin, fout, sout, a, shifts, st));
+        // 64^3 blocks: ux on its own, then uy and uz fused on slabs of the
+        // block (in place on the output when there is no middle buffer)
+        void* mf = midf != nullptr ? midf : fout;
+        float* ms = midf != nullptr ? mids : sout;
+        int rc = run_velocity(g, d, 0, prec, vbc, fin, sin, mf, ms, field, dt, outflow, st);
+        if (rc) return rc;
+        rc = from_hip(launch_kick_yz64(prec, mf, ms, fout, sout, a, shifts, st));
+        if (rc || rho == nullptr) return rc;
+        return run_moments(g, d, prec, fout, sout, rho, umean, nullptr, st);
     }
     if (midf == nullptr) return VLASOV_ERR_WORKSPACE;
     int rc = run_velocity(g, d, 0, prec, vbc, fin, sin, fout, sout, field, dt, outflow, st);

@@ -404,6 +404,25 @@ __global__ void __launch_bounds__(NU * NU) k_kick(const typename Codec<P>::T* __
     }
 }
 
+// The split of every (cell, axis) shift of a kick, one thread each.
+__global__ void __launch_bounds__(256) k_kick_shifts(KickArgs a, KickShift* __restrict__ tab)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * a.cells) return;
+    const long cell = i / 3;
+    const int axis = (int)(i - cell * 3);
+    const LineShift sh = split_shift((double)a.g[(long)axis * a.cells + cell] * a.factor[axis],
+                                     a.nu[axis], a.periodic);
+    KickShift e;
+    e.N = sh.N;
+    e.flags = (sh.neg ? 1 : 0) | (sh.comp ? 2 : 0);
+    e.mu = sh.mu;
+    e.v0 = sh.v0; e.v1 = sh.v1; e.v2 = sh.v2; e.v3 = sh.v3;
+    e.alpha = sh.alpha; e.q = sh.q; e.alpha_c = sh.alpha_c; e.muc = sh.muc;
+    e.pad = 0.0f;
+    tab[i] = e;
+}
+
 // ---------------------------------------------------------------------------
 // uz sweep of long lines (nu_z = 64: a 64^3 FP32 block is 1 MiB, too large
 // for the fused kick): a work-group of 256 threads walks one cell's 4096
@@ -533,23 +552,223 @@ hipError_t launch_vel_uz64(int prec, const void* fin, const float* sin, void* fo
     }
 }
 
-// The split of every (cell, axis) shift of a kick, one thread each.
-__global__ void __launch_bounds__(256) k_kick_shifts(KickArgs a, KickShift* __restrict__ tab)
+// ---------------------------------------------------------------------------
+// uy and uz sweeps of 64^3 velocity blocks fused in LDS.  A 64^3 FP32 block
+// (1 MiB) does not fit a work-group's LDS, but the eight u_x rows of a slab
+// (jx0 .. jx0+7, all jy, all jz: 128 KiB, contiguous in HBM) hold whole
+// u_y-lines and whole u_z-lines, so the last two sweeps of a half step run
+// on it in LDS after the ux sweep (a separate launch).  Persistent
+// work-groups of 512 threads walk cells blockIdx.x, +gridDim.x, ..., each
+// cell's eight slabs in order, with the next slab on its way from HBM into
+// registers while one is swept (the kick's structure); a thread owns one
+// u_y-line and then one u_z-line of the slab.  The line outflows of a cell
+// are summed per thread over its slabs and added to the cell's total, u_y
+// before u_z, by wave 0 in a fixed order.
+// ---------------------------------------------------------------------------
+template <int P>
+struct SlabSlots {
+    using T = typename Codec<P>::T;
+    static constexpr int NU = 64;
+    static constexpr int NT = 512;                 // threads
+    static constexpr int SX = 8;                   // u_x rows per slab
+    static constexpr int SE = SX * NU * NU;        // values per slab
+    static constexpr int NS = SE / (NT * 4);       // 4-value groups per thread
+    Pack<T, 4> q[NS];
+    float sc[NS];
+    __device__ static int elem(int s, int t) { return (s * NT + t) * 4; }
+    // slab k of a block: values k*SE .., uz-lines k*SX*NU ..
+    __device__ void load(const T* src, const float* ssrc, int t)
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int e = elem(s, t);
+            q[s] = *reinterpret_cast<const Pack<T, 4>*>(src + e);
+            sc[s] = Codec<P>::scaled ? ssrc[e / NU] : 1.0f;
+        }
+    }
+    __device__ void put(float* lds, int t) const
+    {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int e = elem(s, t);
+            float* dst = lds + (e / NU) * (NU + 1) + e % NU;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dst[u] = decode<P>(q[s].v[u], sc[s]);
+        }
+    }
+};
+
+// (fin may equal fout, and sin sout: every slab is read whole, by the one
+// work-group that owns it, before that work-group writes it back, so the
+// pointers carry no __restrict__)
+template <int P, bool PER>
+__global__ void __launch_bounds__(512) k_kick_yz64(const typename Codec<P>::T* fin,
+                                                  const float* sin,
+                                                  typename Codec<P>::T* fout,
+                                                  float* sout, KickArgs a,
+                                                  const KickShift* __restrict__ tab)
 {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 3 * a.cells) return;
-    const long cell = i / 3;
-    const int axis = (int)(i - cell * 3);
-    const LineShift sh = split_shift((double)a.g[(long)axis * a.cells + cell] * a.factor[axis],
-                                     a.nu[axis], a.periodic);
-    KickShift e;
-    e.N = sh.N;
-    e.flags = (sh.neg ? 1 : 0) | (sh.comp ? 2 : 0);
-    e.mu = sh.mu;
-    e.v0 = sh.v0; e.v1 = sh.v1; e.v2 = sh.v2; e.v3 = sh.v3;
-    e.alpha = sh.alpha; e.q = sh.q; e.alpha_c = sh.alpha_c; e.muc = sh.muc;
-    e.pad = 0.0f;
-    tab[i] = e;
+    using T = typename Codec<P>::T;
+    using Slots = SlabSlots<P>;
+    constexpr int NU = Slots::NU;
+    constexpr int NT = Slots::NT;
+    constexpr int SX = Slots::SX;
+    constexpr int SE = Slots::SE;
+    constexpr int NSLAB = NU / SX;
+    constexpr long BLK = (long)NU * NU * NU;
+    extern __shared__ float lds[];
+    __shared__ float lmax[Codec<P>::scaled ? NT : 1];
+    __shared__ double red[2 * (NT / 64)];
+    const int t = threadIdx.x;
+    const int ncell = (int)a.cells;            // the launcher checks the range
+    int cell = blockIdx.x;
+    if (cell >= ncell) return;                 // uniform over the work-group
+    // thread t: u_y-line (jx = t / 64, jz = t % 64), then u_z-line (jx, jy = t % 64)
+    const int ybase = (t / NU) * NU * (NU + 1) + (t % NU);
+    const int zbase = t * (NU + 1);
+
+    Slots R;
+    R.load(fin + (long)cell * BLK, sin + (long)cell * NU * NU, fresh_tid());
+    R.put(lds, fresh_tid());
+    int slab = 0;
+    // (cell, slab) of the slab in flight
+    int ncl = NSLAB > 1 ? cell : cell + (int)gridDim.x;
+    int nsl = NSLAB > 1 ? 1 : 0;
+    if (ncl < ncell)
+        R.load(fin + (long)ncl * BLK + (long)nsl * SE, sin + (long)ncl * NU * NU + nsl * SX * NU,
+               fresh_tid());
+    __syncthreads();
+    float oy = 0.0f, oz = 0.0f;
+    for (;;) {
+        LineShift sy, sz;
+        if (tab != nullptr) {
+            const KickShift ey = tab[(long)cell * 3 + 1], ez = tab[(long)cell * 3 + 2];
+            sy.N = ey.N; sy.neg = (ey.flags & 1) != 0; sy.comp = (ey.flags & 2) != 0;
+            sy.mu = ey.mu; sy.v0 = ey.v0; sy.v1 = ey.v1; sy.v2 = ey.v2; sy.v3 = ey.v3;
+            sy.alpha = ey.alpha; sy.q = ey.q; sy.alpha_c = ey.alpha_c; sy.muc = ey.muc;
+            sz.N = ez.N; sz.neg = (ez.flags & 1) != 0; sz.comp = (ez.flags & 2) != 0;
+            sz.mu = ez.mu; sz.v0 = ez.v0; sz.v1 = ez.v1; sz.v2 = ez.v2; sz.v3 = ez.v3;
+            sz.alpha = ez.alpha; sz.q = ez.q; sz.alpha_c = ez.alpha_c; sz.muc = ez.muc;
+        } else {
+            sy = split_shift((double)a.g[a.cells + cell] * a.factor[1], NU, PER);
+            sz = split_shift((double)a.g[2 * a.cells + cell] * a.factor[2], NU, PER);
+        }
+        const int Ny = uniform_sgpr(sy.N), Nz = uniform_sgpr(sz.N);
+        oy += uniform_sgpr(sy.neg ? 1 : 0)
+                  ? kick_axis_dir<P, NU, PER, 1, true>(lds + ybase, sy, Ny, nullptr, nullptr)
+                  : kick_axis_dir<P, NU, PER, 1, false>(lds + ybase, sy, Ny, nullptr, nullptr);
+        __syncthreads();
+        float* sl = Codec<P>::scaled ? sout + (long)cell * NU * NU + slab * SX * NU + t : nullptr;
+        oz += uniform_sgpr(sz.neg ? 1 : 0)
+                  ? kick_axis_dir<P, NU, PER, 2, true>(lds + zbase, sz, Nz, sl, lmax + t)
+                  : kick_axis_dir<P, NU, PER, 2, false>(lds + zbase, sz, Nz, sl, lmax + t);
+        const bool last = slab == NSLAB - 1;
+        const bool ofl = a.outflow != nullptr && !PER;
+        if (ofl && last) {
+            const double wy = wave_sum_f64((double)oy), wz = wave_sum_f64((double)oz);
+            if ((t & 63) == 0) {
+                red[t >> 6] = wy;
+                red[NT / 64 + (t >> 6)] = wz;
+            }
+        }
+        __syncthreads();
+        if (ofl && last && t < 64) {
+            const int k = t < 2 ? t : 0;
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) sum += red[k * (NT / 64) + w];
+            const double ty = read_lane_f64(sum, 0), tz = read_lane_f64(sum, 1);
+            if (t == 0) {
+                double acc = a.outflow[cell];
+                acc += ty * a.du3;
+                acc += tz * a.du3;
+                a.outflow[cell] = acc;
+            }
+        }
+        if (last) {
+            oy = 0.0f;
+            oz = 0.0f;
+        }
+        // store the slab; each slot is refilled with the next slab by the
+        // thread that stored it
+        T* dst = fout + (long)cell * BLK + (long)slab * SE;
+        const int ts = fresh_tid();
+#pragma unroll
+        for (int s = 0; s < Slots::NS; ++s) {
+            const int e = Slots::elem(s, ts);
+            const float* v = lds + (e / NU) * (NU + 1) + e % NU;
+            const float inv = Codec<P>::scaled ? inv_scale(lmax[e / NU]) : 1.0f;
+            Pack<T, 4> q;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) q.v[u] = quantize<P>(v[u], inv);
+            *reinterpret_cast<Pack<T, 4>*>(dst + e) = q;
+        }
+        if (ncl >= ncell) break;
+        R.put(lds, ts);
+        cell = ncl;
+        slab = nsl;
+        nsl = slab + 1;
+        ncl = cell;
+        if (nsl == NSLAB) {
+            nsl = 0;
+            ncl = cell + (int)gridDim.x;
+        }
+        ncl = uniform_sgpr(ncl);
+        nsl = uniform_sgpr(nsl);
+        if (ncl < ncell)
+            R.load(fin + (long)ncl * BLK + (long)nsl * SE,
+                   sin + (long)ncl * NU * NU + nsl * SX * NU, fresh_tid());
+        __syncthreads();
+    }
+}
+
+template <int P>
+static hipError_t launch_kick_yz64_p(const void* fin, const float* sin, void* fout, float* sout,
+                                     const KickArgs& a, const KickShift* tab, hipStream_t st)
+{
+    using T = typename Codec<P>::T;
+    const size_t lds = (size_t)SlabSlots<P>::SX * 64 * 65 * sizeof(float);
+    auto kern = a.periodic ? k_kick_yz64<P, true> : k_kick_yz64<P, false>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern),
+                                                          512, lds)) != hipSuccess)
+        return e;
+    long grid = (long)cus * (per_cu > 0 ? per_cu : 1);
+    if (grid > a.cells) grid = a.cells;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(512), lds, st, (const T*)fin, sin, (T*)fout,
+                       sout, a, tab);
+    return hipGetLastError();
+}
+
+bool kick_yz64_supported(const int nu[3], size_t lds_limit)
+{
+    const size_t lds = (size_t)8 * 64 * 65 * sizeof(float) + 512 * sizeof(float) + 1024;
+    return nu[0] == 64 && nu[1] == 64 && nu[2] == 64 && lds <= lds_limit;
+}
+
+hipError_t launch_kick_yz64(int prec, const void* fin, const float* sin, void* fout, float* sout,
+                            const KickArgs& a, KickShift* shifts, hipStream_t st)
+{
+    if (a.cells == 0) return hipSuccess;
+    if (a.cells > 0x7fffffffL) return hipErrorInvalidValue;   // cell indices are int
+    if (shifts != nullptr) {
+        const long n = 3 * a.cells;
+        hipLaunchKernelGGL(k_kick_shifts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a,
+                           shifts);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    switch (prec) {
+        case PREC_F16: return launch_kick_yz64_p<PREC_F16>(fin, sin, fout, sout, a, shifts, st);
+        case PREC_BF16: return launch_kick_yz64_p<PREC_BF16>(fin, sin, fout, sout, a, shifts, st);
+        default: return launch_kick_yz64_p<PREC_F32>(fin, sin, fout, sout, a, shifts, st);
+    }
 }
 
 template <int P, int N, bool PER>

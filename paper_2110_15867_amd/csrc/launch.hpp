@@ -88,6 +88,11 @@ bool kick_supported(const int nu[3], size_t lds_limit);
 // stream when given, else each work-group splits its shifts itself
 hipError_t launch_kick(int prec, const void* fin, const float* sin, void* fout, float* sout,
                        const KickArgs& a, KickShift* shifts, hipStream_t st);
+// 64^3 blocks: uy and uz fused in LDS on slabs of eight u_x rows (the ux
+// sweep is a separate launch before it); shifts as for launch_kick
+bool kick_yz64_supported(const int nu[3], size_t lds_limit);
+hipError_t launch_kick_yz64(int prec, const void* fin, const float* sin, void* fout, float* sout,
+                            const KickArgs& a, KickShift* shifts, hipStream_t st);
 
 struct MomArgs {
     long cells;

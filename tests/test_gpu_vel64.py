@@ -1,12 +1,12 @@
-"""64^3 velocity blocks (the velocity resolution above the paper's 32^3 runs).
+"""64^3 velocity blocks (the paper's velocity resolution).
 
-A 64^3 FP32 block is 1 MiB, more than a work-group's LDS, so the kick is not
-fused: vlasov_kick / vlasov_step run the three velocity sweeps as separate
-launches (ux and uy one work-group per spatial cell, uz through LDS tiles of
-whole lines).  Checked on the 32^3 x 32^3 workload's recipe (32 density
-modes of amplitude 0.1, drifting field) on a 4^3 x 64^3 grid against the
-FP64 oracle: the kick, two full steps (FP32, to the stated per-step bar) and
-the density after two steps with FP16/BF16 storage.
+A 64^3 FP32 block is 1 MiB, more than a work-group's LDS, so the kick is
+split: ux as a launch of its own, then uy and uz fused in LDS on slabs of
+eight u_x rows (in place on the output for a step's second kick).  Checked
+on the 32^3 x 32^3 workload's recipe (32 density modes of amplitude 0.1,
+drifting field) on a 4^3 x 64^3 grid against the FP64 oracle: the kick, two
+full steps (FP32, to the stated per-step bar) and the density after two
+steps with FP16/BF16 storage.
 """
 import numpy as np
 import pytest
