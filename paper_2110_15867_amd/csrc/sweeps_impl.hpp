@@ -184,8 +184,10 @@ __global__ void __launch_bounds__(256, 4) k_position(const typename Codec<P>::T*
 // coalesced access per row) and runs two select-free walks.  Results are
 // the bits of the per-lane mixed walk.
 // ---------------------------------------------------------------------------
+// (at least six work-groups per CU: 80 VGPRs, six waves per SIMD instead of
+// five; the few values this spills cost less than the latency it hides)
 template <int P, int MT, int H>
-__global__ void __launch_bounds__(256) k_position_pair(const typename Codec<P>::T* __restrict__ fin,
+__global__ void __launch_bounds__(256, 6) k_position_pair(const typename Codec<P>::T* __restrict__ fin,
                                                        const float* __restrict__ sin,
                                                        typename Codec<P>::T* __restrict__ fout,
                                                        float* __restrict__ sout, PosArgs a)
