@@ -112,3 +112,52 @@ def test_scaled_storage_density(prec):
     print(f"density rel L2 {rel_l2:.2e}", flush=True)
     assert rel_l2 <= 2e-3
     assert float(V.decode(st).min()) >= 0.0
+
+
+@pytest.mark.parametrize("vbc", [V.VBC_OUTFLOW, V.VBC_PERIODIC])
+@pytest.mark.parametrize("prec", [V.F32, V.F16])
+def test_kick_large_shifts(prec, vbc):
+    """The split kick with shifts of up to 2.7 cells on every velocity axis
+    (integer parts translated after the update) and both velocity
+    boundaries.  FP32: against the oracle's three sweeps.  FP16: the ux
+    launch is the public ux sweep (checked on its own elsewhere), so the
+    kick's output is held against the oracle's uy and uz sweeps of the
+    decoded ux result, to within its own codes' rounding."""
+    n, nu = (2, 2, 2), (64, 64, 64)
+    print("case: kick large shifts", V.PREC_NAME[prec], vbc, flush=True)
+    og = oracle.Grid.make(n, nu, (1.0, 1.0, 1.0), (1.0, 1.0, 1.0))
+    hg = V.make_grid(n, nu, (1.0, 1.0, 1.0), (1.0, 1.0, 1.0))
+    rng = np.random.default_rng(64 + vbc)
+    f32 = rng.uniform(0.0, 1.0, og.shape).astype(np.float32) ** 2
+    cells = int(np.prod(n))
+    dt = 0.1
+    du = 2.0 / 64
+    s = rng.uniform(-2.7, 2.7, (3, cells))
+    s[:, 0] = [1.0, -2.0, 0.0]                      # whole-cell shifts too
+    g = (s * du / dt).astype(np.float32).reshape((3,) + n)
+    gt = torch.from_numpy(g).cuda()
+    st = V.encode(hg, prec, torch.from_numpy(f32).cuda())
+    fin = V.decode(st).double().cpu().numpy()
+    ofl_ref = np.zeros(cells)
+    if prec == V.F32:
+        want = oracle.kick(og, fin, g, dt, vbc=vbc, outflow=ofl_ref)
+    else:
+        ofl_ux = torch.zeros(n, dtype=torch.float64, device="cuda")
+        mid = V.advect("ux", st, dt, g=gt, vbc=vbc, outflow=ofl_ux)
+        torch.cuda.synchronize()
+        ofl_ref += ofl_ux.cpu().numpy().reshape(-1)
+        want = V.decode(mid).double().cpu().numpy()
+        for axis in (1, 2):
+            want = oracle.advect_velocity(og, axis, want, g, dt, vbc=vbc, outflow=ofl_ref)
+    ofl = torch.zeros(n, dtype=torch.float64, device="cuda")
+    out = V.kick(st, gt, dt, vbc=vbc, outflow=ofl)
+    torch.cuda.synchronize()
+    got = V.decode(out).double().cpu().numpy()
+    tol = 1e-5 * float(fin.max())
+    if prec != V.F32:
+        tol = tol + 1.01 * 2.0 ** -11 * out.scale.double().cpu().numpy()[..., None]
+    assert np.all(np.abs(got - want) <= tol)
+    assert float(got.min()) >= 0.0
+    if vbc == V.VBC_OUTFLOW:
+        np.testing.assert_allclose(ofl.cpu().numpy().reshape(-1), ofl_ref, rtol=1e-4,
+                                   atol=1e-6 * float(fin.max()) * du ** 3 * 64 ** 2)
