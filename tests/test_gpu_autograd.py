@@ -130,7 +130,10 @@ def test_gradients_finite_differences(adjoint_workload):
             rel = abs(fd - an) / max(abs(fd), 1e-30)
             worst = max(worst, rel)
             print(f"direction {k:2d}: fd {fd:+.6e} adjoint {an:+.6e} rel {rel:.2e}")
-            assert an == pytest.approx(fd, rel=2e-2)
+            # measured worst 9.4e-4 (field directions: a shifted field moves
+            # the fractional shifts, and with them selections, within the
+            # steps); FP32 rounding of the loss alone is ~1e-7 / h
+            assert an == pytest.approx(fd, rel=5e-3)
     print(f"worst relative difference {worst:.2e}")
 
 
