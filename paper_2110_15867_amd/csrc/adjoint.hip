@@ -310,9 +310,10 @@ template <int MT, class R>
 __device__ float line_adjoint(R& rx, R& rl, float* lam_in, long stride, int Mrt, int dir,
                               const LineShift& sh, bool periodic)
 {
-    // MT > 0: the line length at compile time (the walk itself stays a loop:
-    // unrolled, its inlined linearisations need more registers than a SIMD
-    // has for two waves)
+    // MT > 0: the line length at compile time.  The walk is unrolled by five,
+    // the length of the interface window below, so that its slots are renamed
+    // instead of moved at every interface (unrolled whole, its inlined
+    // linearisations need more registers than a SIMD has for two waves)
     const int M = MT > 0 ? MT : Mrt;
     const WeightSlopes ds = sl5_weight_slopes(sh.mu);
     const int N = sh.N;
@@ -330,7 +331,7 @@ __device__ float line_adjoint(R& rx, R& rl, float* lam_in, long stride, int Mrt,
     // identity term source: lam_{r+N} for r = j-2 -> read separately
     R rid = rl;
     rid.seek(N);                                     // lam_{0+N}
-#pragma unroll 1
+#pragma unroll 5
     for (int j = -2; j <= M + 1; ++j) {
         if (j > -2) {
             for (int q = 0; q < 4; ++q) wx[q] = wx[q + 1];
