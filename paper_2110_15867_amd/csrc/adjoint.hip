@@ -83,6 +83,14 @@ __device__ __forceinline__ Lin lin_comb(float p, const Lin& x, float q, const Li
     return r;
 }
 
+__device__ __forceinline__ Lin lin_scale(float p, const Lin& x)
+{
+    Lin r;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) r.w[i] = p * x.w[i];
+    return r;
+}
+
 // A value with its linear form.
 struct VL {
     float v;
@@ -224,7 +232,7 @@ __device__ FluxLin flux_lin(const Stencil& s, const LineShift& sh, const WeightS
             F = mp_bounded_lin(F, s, u, sh.alpha, a_mu);
         }
         // positivity clamp med3(mu L, 0, c), oracle tie rules
-        VL pre{sh.mu * F.v, lin_comb(sh.mu, F.l, 0.0f, F.l)};
+        VL pre{sh.mu * F.v, lin_scale(sh.mu, F.l)};
         pre.l.w[5] = fmaf(sh.mu, F.l.w[5], F.v);
         const Pick k = pmed3(Pick{pre.v, 0}, Pick{0.0f, 1}, Pick{s.c, 2});
         r.v = k.v;
@@ -246,7 +254,7 @@ __device__ FluxLin flux_lin(const Stencil& s, const LineShift& sh, const WeightS
             const Lin u[5] = {lin_unit(4), lin_unit(3), lin_unit(2), lin_unit(1), lin_unit(0)};
             G = mp_bounded_lin(G, mst, u, sh.alpha_c, ac_mu);
         }
-        VL P{sh.muc * G.v, lin_comb(sh.muc, G.l, 0.0f, G.l)};
+        VL P{sh.muc * G.v, lin_scale(sh.muc, G.l)};
         P.l.w[5] = sh.muc * G.l.w[5] - G.v;
         const Pick k = pmed3(Pick{P.v, 0}, Pick{0.0f, 1}, Pick{s.c, 2});
         const Lin psi = k.id == 0 ? P.l : (k.id == 1 ? lin_zero() : uc);
