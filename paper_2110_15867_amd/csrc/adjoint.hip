@@ -125,6 +125,22 @@ __device__ __forceinline__ Pick pminmod4(const Pick& w, const Pick& x, const Pic
     return Pick{0.0f, 4};
 }
 
+// curv_minmod on (value, candidate): the value with curv_minmod's FP32
+// operations (so the bounds that use it are the forward's), the candidate
+// the oracle's minmod of four picks where its value is the same, else the
+// one the value came from (m = minmod(Da, Db), or 4m - o with o the other).
+__device__ __forceinline__ Pick pcurv_minmod(float Da, float Db)
+{
+    const float v = curv_minmod(Da, Db);
+    const Pick w = pminmod4(Pick{fmaf(4.0f, Da, -Db), 0}, Pick{fmaf(4.0f, Db, -Da), 1},
+                            Pick{Da, 2}, Pick{Db, 3});
+    if (w.v == v) return Pick{v, w.id};
+    if (v == 0.0f) return Pick{v, 4};
+    const bool a_least = med3(Da, Db, 0.0f) == Da;
+    if (v == (a_least ? Da : Db)) return Pick{v, a_least ? 2 : 3};
+    return Pick{v, a_least ? 0 : 1};
+}
+
 // Form of the curvature minmod that won: candidates 4 Da - Db (0),
 // 4 Db - Da (1), Da (2), Db (3), zero (4).
 __device__ __forceinline__ Lin minmod_form(int id, const Lin& Da, const Lin& Db)
@@ -154,13 +170,11 @@ __device__ VL mp_bounded_lin(const VL& fhat, const Stencil& s, const Lin (&u)[5]
 {
     const float Dmv = s.dm1 - s.dm2, D0v = s.d0 - s.dm1, Dpv = s.dp1 - s.d0;
     // curv_minmod(Da, Db) = minmod(4Da-Db, 4Db-Da, Da, Db)
-    const Pick Mp = pminmod4(Pick{fmaf(4.0f, D0v, -Dpv), 0}, Pick{fmaf(4.0f, Dpv, -D0v), 1},
-                             Pick{D0v, 2}, Pick{Dpv, 3});
-    const Pick Mm = pminmod4(Pick{fmaf(4.0f, Dmv, -D0v), 0}, Pick{fmaf(4.0f, D0v, -Dmv), 1},
-                             Pick{Dmv, 2}, Pick{D0v, 3});
+    const Pick Mp = pcurv_minmod(D0v, Dpv);
+    const Pick Mm = pcurv_minmod(Dmv, D0v);
     const Pick c{s.c, 0};
     const Pick d{s.d, 1};
-    const Pick fMD{0.5f * ((s.c + s.d) - Mp.v), 2};
+    const Pick fMD{fmaf(-0.5f, Mp.v, fmaf(0.5f, s.d0, s.c)), 2};
     const Pick fUL{fmaf(alpha, s.dm1, s.c), 3};
     const Pick fLC{fmaf(4.0f / 3.0f, Mm.v, fmaf(0.5f, s.dm1, s.c)), 4};
     const Pick lo = pmax2(pmin2(pmin2(c, d), fMD), pmin2(pmin2(c, fUL), fLC));

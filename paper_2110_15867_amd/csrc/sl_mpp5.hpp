@@ -237,14 +237,18 @@ __device__ __forceinline__ float med3(float a, float b, float c)
 }
 
 // minmod(4Da-Db, 4Db-Da, Da, Db): least magnitude when all four share a
-// strict sign, else 0.  The two-argument minmod is med3(x, y, 0), and the
-// four-argument one is the minmod of two such pairs: three medians, no
-// min/max (whose operands the compiler would first have to canonicalise).
+// strict sign, else 0.  The two-argument minmod is med3(x, y, 0).  Let m =
+// minmod(Da, Db) and o the other curvature.  When Da and Db share a strict
+// sign, |4o - m| >= 3|o| >= |m| with the sign of o, so 4o - m never has the
+// least magnitude, and the result is m or 4m - o, whichever is smaller in
+// magnitude, or 0 where 4m - o has the other sign: med3(m, 4m - o, 0).
+// Otherwise m = 0 and so is that median.  4m - o = 5m - (Da + Db): four
+// operations instead of five, symmetric in Da and Db (as the carry between
+// interfaces needs), and within one rounding of Da + Db of the four-way form.
 __device__ __forceinline__ float curv_minmod(float Da, float Db)
 {
-    const float p = fmaf(4.0f, Da, -Db);
-    const float q = fmaf(4.0f, Db, -Da);
-    return med3(med3(p, q, 0.0f), med3(Da, Db, 0.0f), 0.0f);
+    const float m = med3(Da, Db, 0.0f);
+    return med3(m, fmaf(5.0f, m, -(Da + Db)), 0.0f);
 }
 
 __device__ __forceinline__ float curvature(float l, float c, float r)
@@ -266,7 +270,8 @@ __device__ __forceinline__ float mp_bounded_m(float fhat, const Stencil& s, floa
                                               float Mp)
 {
     const float fUL = fmaf(alpha, s.dm1, s.c);
-    const float fMD = 0.5f * ((s.c + s.d) - Mp);
+    // the mean of f_j and f_{j+1} as f_j + d0 / 2, minus half the minmod
+    const float fMD = fmaf(-0.5f, Mp, fmaf(0.5f, s.d0, s.c));
     const float fLC = fmaf(4.0f / 3.0f, Mm, fmaf(0.5f, s.dm1, s.c));
     const float lo = fmaxf(fminf(fminf(s.c, s.d), fMD), fminf(fminf(s.c, fUL), fLC));
     const float hi = fminf(fmaxf(fmaxf(s.c, s.d), fMD), fmaxf(fmaxf(s.c, fUL), fLC));
@@ -343,12 +348,13 @@ __device__ __forceinline__ float flux_mag(const Stencil& s, const LineShift& sh)
 // d^M4 at j+1/2 is d^M4 at j-1/2 of the next interface (the minmod is
 // symmetric in its two curvatures, so the values are the very bits
 // mp_bounded would compute), so one minmod per interface is evaluated
-// outside the test and the bounds left behind it cost eleven operations.
+// outside the test and the bounds left behind it cost ten operations.
 // The mirrored stencil of a comp line swaps the two.  Same result as
 // flux_mag, bit for bit.
 // UNI: branch on the line's comp flag (as mp_flux<true>); otherwise each lane
 // picks its orientation by select (as mp_flux<false>) -- mp_bounded_m reads
-// only c, d, dm1 and the two minmods of the stencil, so four selects orient it.
+// only c, d, d0, dm1 and the two minmods of the stencil, so five selects
+// orient it.
 template <bool UNI = true>
 __device__ __forceinline__ float flux_mag_mm(const Stencil& s, const LineShift& sh, float Mm,
                                              float Mp)
@@ -374,6 +380,7 @@ __device__ __forceinline__ float flux_mag_mm(const Stencil& s, const LineShift& 
             const float ac = mp_alpha(sh.muc);
             Stencil t = s;
             t.d = c ? s.b : s.d;
+            t.d0 = c ? -s.dm1 : s.d0;
             t.dm1 = c ? -s.d0 : s.dm1;
             const float fh = c ? fmaf(-q, y, s.c) : s.c + y;
             const float lim = mp_bounded_m(fh, t, c ? ac : sh.alpha, c ? Mp : Mm, c ? Mm : Mp);
