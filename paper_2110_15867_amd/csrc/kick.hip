@@ -105,7 +105,7 @@ template <int M, int S, bool NEG, bool PER>
 __device__ __forceinline__ float translate_line(float* line, int N, float phi_top)
 {
     auto at = [&](int p) -> float& { return line[(NEG ? M - 1 - p : p) * S]; };
-    if (PER) {
+    if (PER && M <= 32) {
         float z[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) z[k] = at(k);
@@ -115,6 +115,23 @@ __device__ __forceinline__ float translate_line(float* line, int N, float phi_to
             p = p >= M ? p - M : p;
             at(p) = z[k];
         }
+        return 0.0f;
+    }
+    if (PER) {
+        // 64-value lines: the rotation in place, as three reversals (all
+        // positions, then 0..N-1 and N..M-1), so that no copy of the line
+        // holds registers for the whole kernel (with one, the tiled uz
+        // kernel needed 276 registers and spilled)
+        auto rev = [&](int lo, int hi) {
+            for (int i = lo, j = hi - 1; i < j; ++i, --j) {
+                const float u = at(i);
+                at(i) = at(j);
+                at(j) = u;
+            }
+        };
+        rev(0, M);
+        rev(0, N);
+        rev(N, M);
         return 0.0f;
     }
     float acc = 0.0f;

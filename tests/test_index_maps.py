@@ -15,7 +15,9 @@ kernels' maps must keep them (and this restatement must follow).
   (cell, slab) pairs;
 * the 4-value slots of the fused kick's block (k_kick), the 64-cell uz tiles
   (k_vel_uz_tiles) and the slabs (k_kick_yz64): consecutive threads take
-  consecutive 16-byte groups, and each lands in its padded LDS line.
+  consecutive 16-byte groups, and each lands in its padded LDS line;
+* the in-place rotation of a periodic 64-value line by the integer part of
+  its shift (translate_line: three reversals, in either walk direction).
 """
 import numpy as np
 import pytest
@@ -140,3 +142,34 @@ def test_slots_fill_the_padded_lds_once(nthreads, nvalues, nu):
     pos = ((line * (nu + 1) + off)[..., None] + np.arange(4)).ravel()
     assert len(np.unique(pos)) == nvalues
     assert pos.max() < (nvalues // nu) * (nu + 1)
+
+
+def rotate_by_reversals(line, N, neg):
+    """translate_line's periodic rotation of a 64-value line in place: frame
+    position p at index (M-1-p if neg else p); reverse all positions, then
+    0..N-1 and N..M-1."""
+    M = len(line)
+    x = list(line)
+    at = (lambda p: M - 1 - p) if neg else (lambda p: p)
+
+    def rev(lo, hi):
+        i, j = lo, hi - 1
+        while i < j:
+            x[at(i)], x[at(j)] = x[at(j)], x[at(i)]
+            i, j = i + 1, j - 1
+    rev(0, M)
+    rev(0, N)
+    rev(N, M)
+    return np.array(x)
+
+
+@pytest.mark.parametrize("neg", [False, True])
+def test_periodic_rotation_in_place(neg):
+    # out_{p+N mod M} = y_p in frame positions; the frame runs against the
+    # index for lines whose upwind direction is -u
+    M = 64
+    y = np.arange(M) * 1.0 + 0.5
+    for N in range(1, M):
+        got = rotate_by_reversals(y, N, neg)
+        want = np.roll(y, -N if neg else N)
+        assert np.array_equal(got, want), N
