@@ -413,7 +413,20 @@ __global__ void __launch_bounds__(256) k_position_adj(const float* __restrict__ 
 {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.O * a.I) return;
-    const long o = t / a.I, k = t - (t / a.I) * a.I;
+    const long o = t / a.I;
+    long k = t - o * a.I;
+    // y sweeps (the shift follows u_y, pst = nu_z): consecutive lanes would
+    // cover 64 / nu_z values of u_y, and a wave would run both sides of every
+    // branch on the shift.  Instead each wave takes one u_y: 64 / nu_z whole
+    // uz-lines from consecutive u_x rows -- a permutation of k within groups
+    // of 64 nu_y elements (64 / nu_z u_x rows), which tile every row
+    if (a.pst == a.nuz && a.nshift > 1 && a.nshift * a.nuz * a.nux == a.Nu && a.nuz <= 64 &&
+        64 % a.nuz == 0 && a.nux % (64 / a.nuz) == 0) {
+        const long G = 64L * a.nshift;
+        const long l = k & 63;
+        const long rr = l / a.nuz;
+        k = (k / G) * G + (rr * a.nshift + (k % G) / 64) * a.nuz + (l - rr * a.nuz);
+    }
     const int jl = (int)(((k % a.Nu) / a.pst) % a.nshift);
     const LineShift sh = split_shift(a.shift[jl], a.M, true);
     const int dir = sh.neg ? -1 : 1;

@@ -17,7 +17,8 @@ kernels' maps must keep them (and this restatement must follow).
   (k_vel_uz_tiles) and the slabs (k_kick_yz64): consecutive threads take
   consecutive 16-byte groups, and each lands in its padded LDS line;
 * the in-place rotation of a periodic 64-value line by the integer part of
-  its shift (translate_line: three reversals, in either walk direction).
+  its shift (translate_line: three reversals, in either walk direction);
+* the y-sweep adjoint's permutation (k_position_adj): one u_y per wave.
 """
 import numpy as np
 import pytest
@@ -173,3 +174,25 @@ def test_periodic_rotation_in_place(neg):
         got = rotate_by_reversals(y, N, neg)
         want = np.roll(y, -N if neg else N)
         assert np.array_equal(got, want), N
+
+
+def adjoint_y_map(nz, nux, nuy, nuz):
+    """k_position_adj's element of thread k of a row for y sweeps (pst = nu_z)."""
+    I = nz * nux * nuy * nuz
+    k = np.arange(I)
+    G = 64 * nuy
+    l = k & 63
+    rr = l // nuz
+    return (k // G) * G + (rr * nuy + (k % G) // 64) * nuz + (l - rr * nuz)
+
+
+@pytest.mark.parametrize("nz,nux,nuy,nuz", [(32, 16, 16, 16), (3, 4, 6, 16), (2, 2, 5, 32),
+                                            (1, 1, 3, 64), (2, 8, 8, 8)])
+def test_adjoint_y_map(nz, nux, nuy, nuz):
+    if not (nux % (64 // nuz) == 0):
+        pytest.skip("the kernel keeps the consecutive map")
+    kk = adjoint_y_map(nz, nux, nuy, nuz)
+    assert np.array_equal(np.sort(kk), np.arange(len(kk)))          # a permutation
+    jy = ((kk % (nux * nuy * nuz)) // nuz) % nuy
+    w = jy.reshape(-1, 64)
+    assert np.all(w == w[:, :1])                                     # one u_y per wave
